@@ -1,0 +1,227 @@
+"""Benchmark of the relational hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload 1] [--no-cpu-baseline]
+
+A step is one pass of the plain per-operator pipeline over the one-GPU share
+(200M fact rows x 25M dim rows, ~1.5M groups, 64 buckets), inputs resident in
+HBM before timing starts:
+
+    radix partition (64 buckets, 4 columns + row id) -> filter (date < 1500)
+    -> join build (25M keys) -> join probe -> group-by (exact int128 sums)
+    -> float64 averages -> top-100 of price over the selection
+
+Prints one JSON line.  `value` is the whole step's algorithmic HBM bytes (what
+each operator must read and write once) divided by the step time.  Per-kernel
+durations come from HIP events recorded on the stream each kernel runs on.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "HBM GB/s (% peak) for partition/join/group-by; served p50/p99 query latency"
+
+
+def algorithmic_bytes(n: int, m: int, s_n: int, groups: int, k: int, partition: bool = True) -> dict:
+    """Bytes each operator must move once (inputs read once, outputs written
+    once, one 16-byte slot per build insert or probe lookup)."""
+    ops = {
+        "partition": (36 + 40) * n if partition else 0,        # 5 columns in, 5 columns + row id out
+        "filter": 4 * n + 4 * s_n,                             # date in, selection out
+        "join_build": (12 + 16) * m,                           # key + payload in, slot written
+        "join_probe": (4 + 8 + 16 + 8) * s_n,                  # sel + fk in, slot read, pair out
+        "groupby": (4 + 4 + 24) * s_n + 36 * groups,           # row id + key + 3 values in, groups out
+        "topk": (4 + 8) * s_n + 12 * k,                        # sel + price in, k rows out
+    }
+    return ops
+
+
+# kernel -> (operator whose algorithmic bytes it carries)
+KERNEL_OP = {
+    "gq_partition_scatter": "partition",
+    "gq_filter": "filter",
+    "gq_join_build": "join_build",
+    "gq_join_probe": "join_probe",
+    "gq_groupby_bucket": "groupby",
+    "gq_topk_local": "topk",
+}
+KERNELS = ["gq_zero", "gq_partition_hist", "gq_scan", "gq_partition_offsets", "gq_partition_scatter", "gq_filter",
+           "gq_join_init", "gq_join_build", "gq_join_probe", "gq_groupby_hist", "gq_groupby_scatter",
+           "gq_groupby_bucket", "gq_groupby_emit", "gq_groupby_local", "gq_topk_local", "gq_topk_merge"]
+
+
+def _file_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or None
+    if there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            a, b = line.split(":", 1)
+            kv[a.strip()] = b.strip()
+    src = os.path.join(ROOT, "paper_2506_09226_amd", "csrc", kv.get("source", ""))
+    if not os.path.exists(src) or _file_sha(src) != kv.get("source_sha256_16"):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, sample_rows: int) -> dict:
+    """The oracle, single threaded, on the first `sample_rows` fact rows with the
+    full dimension table; reported in the same unit (algorithmic GB/s)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    spec = synth.FactSpec(sample_rows, w.fact.m, w.fact.seed)
+    fact = {k: v.numpy() for k, v in synth.fact_table(spec).items()}
+    dim = {k: v.numpy() for k, v in synth.dim_table(w.dim_m, w.dim_seed, w.attr_range).items()}
+    oracle.lib()
+    t0 = time.perf_counter()
+    pk, pcols, prow_id, poff = oracle.partition(fact["fk"], w.log2_fanout,
+                                                [fact[c] for c in ("date", "qty", "price", "disc")])
+    pdate, pqty, pprice, pdisc = pcols
+    sel = oracle.filter(pdate, -(1 << 31), w.date_hi)
+    prow, pay = oracle.join(dim["key"], dim["attr"], pk, sel)
+    g = oracle.groupby(len(prow), pqty, pprice, pdisc, rowid=prow, key32=pay)
+    oracle.topk(pprice, 100, sel=sel)
+    dt = time.perf_counter() - t0
+    by = algorithmic_bytes(sample_rows, w.dim_m, len(sel), len(g["count"]), 100)
+    return {"value": round(sum(by.values()) / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_rows:,} of {w.fact.n:,} fact rows with all {w.dim_m:,} dim rows; "
+                      f"same pipeline, single-threaded C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--cpu-sample", type=int, default=16_777_216)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU exchange is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2506_09226_amd as gq
+    from paper_2506_09226_amd.pipeline import PlainPipeline
+
+    w = synth.workload(args.workload)
+    torch.cuda.set_device(0)
+    ctx = gq.Context(0)
+    t_gen = time.perf_counter()
+    fact = synth.fact_table(w.fact, device="cuda")
+    dim = synth.dim_table(w.dim_m, w.dim_seed, w.attr_range, device="cuda")
+    torch.cuda.synchronize()
+    print(f"# generated {w.fact.n:,} x {w.dim_m:,} rows in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=w.log2_fanout, topk=100)
+
+    for _ in range(args.warmup):
+        pl.step()
+    torch.cuda.synchronize()
+    ctx.raise_status()
+    s_n = int(pl.n_sel.item())
+    groups = int(pl.groups.n_groups.item())
+
+    # timed region: whole steps, stream-ordered, no host waits inside
+    stream = torch.cuda.current_stream()
+    if not args.no_timing:
+        ctx.reset_timing()
+        ctx.set_timing(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        pl.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    ctx.set_timing(False)
+    ctx.raise_status()
+    print(f"# {args.steps} steps: {ms_step:.3f} ms/step (host wall {1e3 * wall / args.steps:.3f} ms/step)",
+          file=sys.stderr, flush=True)
+
+    by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100)
+    total_bytes = sum(by.values())
+    kern = {}
+    if not args.no_timing:
+        for k in KERNELS:
+            cnt, ms = ctx.kernel_time(k)
+            if cnt:
+                kern[k] = {"launches": cnt, "avg_ms": ms / cnt, "ms_per_step": ms / args.steps}
+    ops = {}
+    for k, op in KERNEL_OP.items():
+        if k in kern:
+            ops[op] = {"kernel": k, "avg_ms": round(kern[k]["avg_ms"], 4), "bytes": by[op],
+                       "GB/s": round(by[op] / (kern[k]["avg_ms"] * 1e6), 1),
+                       "frac_of_peak": round(by[op] / (kern[k]["avg_ms"] * 1e6) / HBM_PEAK_GBS, 4)}
+    roofline = None
+    if kern:
+        dom = max(KERNEL_OP, key=lambda k: kern.get(k, {}).get("ms_per_step", 0.0))
+        op = KERNEL_OP[dom]
+        ach = by[op] / (kern[dom]["avg_ms"] * 1e6)
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(dom, f"{w.fact.n // 1_000_000}M"),
+                    "algorithmic_bytes_per_launch": by[op]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(total_bytes / (ms_step * 1e6), 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "fact_rows": w.fact.n, "dim_rows": w.dim_m, "groups": groups,
+                   "selected_rows": s_n, "buckets": 1 << w.log2_fanout, "filter": f"date < {w.date_hi}",
+                   "topk": 100, "form": "plain (one launch chain per operator)"},
+        "hbm_frac_of_peak": round(total_bytes / (ms_step * 1e6) / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_step": total_bytes,
+        "rows_per_s": round(w.fact.n / (ms_step * 1e-3)),
+        "ops": ops,
+        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.fact.n))
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

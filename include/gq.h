@@ -1,0 +1,281 @@
+/*
+ * gq.h -- C ABI of the per-GPU relational hot path (MI355X / gfx950).
+ *
+ * The library implements, on one GPU's share of the data, the local
+ * relational operators of a data-parallel SQL engine whose exchange steps
+ * (shuffle, broadcast, all-reduce) are built from collective-communication
+ * primitives (Wu et al., "Terabyte-Scale Analytics in the Blink of an Eye",
+ * Sec. 2).  The paper runs these operators as tensor programs and states only
+ * their semantics; the kernels behind this header are hand-written HIP.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory.  Every pointer argument named *_dev, every column, table,
+ *    output and workspace pointer is DEVICE memory owned by the caller (e.g.
+ *    from torch.empty(..., device="cuda")).  Arrays passed as "host array"
+ *    are host memory read before the call returns.  The library never frees
+ *    caller memory and never allocates memory that it hands back.
+ *  - Streams.  gq_stream is a hipStream_t (NULL = the null stream).  Every
+ *    operator is asynchronous and stream ordered; counts are written to
+ *    device memory so that operators chain without host round trips.
+ *  - Counts.  An input count is given as a host bound `n` (sizes the launch)
+ *    plus an optional device scalar `n_dev` (int64); when `n_dev` is non-NULL
+ *    the operator uses min(*n_dev, n) rows, read on the device.
+ *  - Row ids are int32: tables have at most 2^31 - 1 rows.
+ *  - Workspace.  Operators that need scratch memory take (ws, ws_bytes);
+ *    the required size comes from the matching *_workspace_bytes() query.  A
+ *    workspace must not be shared by calls that may run concurrently.
+ *  - Errors.  Argument errors are detected on the host and returned
+ *    synchronously (GQ_ERR_INVALID_ARG, GQ_ERR_WORKSPACE, GQ_ERR_UNSUPPORTED);
+ *    nothing is launched then.  Data-dependent errors found by a kernel
+ *    (duplicate or invalid build key, a full table) are recorded in a
+ *    per-context device status word and read with gq_status_word(), which
+ *    synchronizes the stream.  After such an error the outputs of that call
+ *    are unspecified.  gq_last_error() returns a message for the last non-OK
+ *    host-side status.
+ *  - Results.  Filter, partition, probe and top-k outputs are deterministic
+ *    and ordered.  Group output order is unspecified.  Every integer result
+ *    is exact and independent of scheduling.
+ */
+#ifndef GQ_H
+#define GQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gq_status;
+#define GQ_OK                 0
+#define GQ_ERR_INVALID_ARG    1  /* bad pointer, size or parameter            */
+#define GQ_ERR_CAPACITY       2  /* a table or output capacity was exceeded   */
+#define GQ_ERR_WORKSPACE      3  /* workspace missing or smaller than needed  */
+#define GQ_ERR_DUPLICATE_KEY  4  /* two build rows carry the same key         */
+#define GQ_ERR_HIP            5  /* a HIP runtime call failed                 */
+#define GQ_ERR_UNSUPPORTED    6  /* parameter outside the supported range     */
+#define GQ_ERR_INVALID_KEY    7  /* build key equal to the empty-slot marker  */
+
+/* Column element types; the value is the element width in bytes. */
+#define GQ_I32 4
+#define GQ_I64 8
+
+typedef void *gq_stream;                 /* hipStream_t */
+typedef struct gq_ctx gq_ctx;            /* opaque, one per device */
+
+/* ------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (allocates a few bytes of device
+ * memory for the status word).  *out receives the context.
+ * Errors: GQ_ERR_INVALID_ARG (out NULL, bad device), GQ_ERR_HIP. */
+gq_status gq_ctx_create(int device, gq_ctx **out);
+
+/* Destroy a context created by gq_ctx_create (NULL is ignored). */
+void gq_ctx_destroy(gq_ctx *ctx);
+
+/* Message for the last non-OK status returned on this context ("" if none).
+ * The string is owned by the context and valid until its next call. */
+const char *gq_last_error(const gq_ctx *ctx);
+
+/* Synchronize `stream`, then read and clear the device status word: *out is
+ * GQ_OK or the first device-side error recorded since the last read
+ * (GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY or GQ_ERR_CAPACITY).
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
+gq_status gq_status_word(gq_ctx *ctx, gq_stream stream, gq_status *out);
+
+/* Per-kernel timing with HIP events recorded on the stream each kernel is
+ * launched on (off by default).  gq_kernel_time synchronizes the device and
+ * returns, for the kernel named `name`, the number of timed launches and their
+ * summed duration in milliseconds since the last reset.
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
+gq_status gq_set_timing(gq_ctx *ctx, int enable);
+gq_status gq_kernel_time(gq_ctx *ctx, const char *name, int64_t *launches, double *total_ms);
+gq_status gq_reset_timing(gq_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Scan + filter
+ * Paper: Sec. 2.2 (the example plan filters both inputs of a join with
+ * their predicates before the exchange and the join).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for gq_filter over at most n rows. */
+size_t gq_filter_workspace_bytes(int64_t n);
+
+/* sel_out = the row ids r with lo <= col[r] < hi, in ascending order of r
+ * (when sel_in is NULL, r ranges over 0..n-1), or the entries r of sel_in
+ * that satisfy the predicate, in sel_in's order.
+ *   col        device, `dtype` (GQ_I32 or GQ_I64) elements, indexed by row id
+ *   n          with sel_in NULL: rows of col; else: host bound on the length
+ *              of sel_in, with n_dev (nullable) its device length
+ *   sel_out    device int32, capacity >= n
+ *   n_out_dev  device int64 scalar, receives the output length
+ * Errors: GQ_ERR_INVALID_ARG (NULL col/sel_out/n_out_dev, n < 0 or > 2^31-1,
+ * bad dtype), GQ_ERR_WORKSPACE. */
+gq_status gq_filter(gq_ctx *ctx, const void *col, int dtype, int64_t n, const int64_t *n_dev,
+                    const int32_t *sel_in, int64_t lo, int64_t hi,
+                    int32_t *sel_out, int64_t *n_out_dev,
+                    void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Radix hash partition (the local half of a shuffle)
+ * Paper: Sec. 2.2 (every process applies the same partitioning function to
+ * its rows; the shuffle redistributes the partitions, keeping the total data
+ * fixed) and Sec. 2.3 (sizes are exchanged first; each column is received
+ * into one contiguous buffer at per-sender start offsets).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for partitioning n rows into 2^log2_fanout buckets. */
+size_t gq_radix_partition_workspace_bytes(int64_t n, int log2_fanout);
+
+/* bucket(r) = top log2_fanout bits of fmix64((uint64)key[r]), where fmix64 is
+ * the 64-bit finalizer of MurmurHash3.  Rows are written bucket by bucket,
+ * keeping their input order inside a bucket (stable), into contiguous
+ * per-column output buffers:
+ *   key_out[offsets[b] .. offsets[b+1])       keys of bucket b
+ *   cols_out[c][same range]                   column c of the same rows
+ *   rowid_out[same range]                     source row ids (nullable)
+ *   offsets_dev                               device int64[P+1], offsets[0]=0,
+ *                                             offsets[P]=n (exclusive prefix
+ *                                             sums of the bucket sizes)
+ *   key        device int64[n]
+ *   cols       host array of `ncols` device pointers, column c has n
+ *              elements of col_bytes[c] (4 or 8) bytes; cols_out likewise
+ *   ncols      0..8
+ *   log2_fanout 0..8 (1..256 buckets)
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_UNSUPPORTED (fan-out or column count
+ * outside the range), GQ_ERR_WORKSPACE. */
+gq_status gq_radix_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log2_fanout,
+                             int ncols, const void *const *cols, const int32_t *col_bytes,
+                             int64_t *key_out, void *const *cols_out, int32_t *rowid_out,
+                             int64_t *offsets_dev, void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Hash equi-join (build + probe)
+ * Paper: Sec. 2.2 (a join of partitioned tables runs locally once both sides
+ * are partitioned on the join key, after a broadcast or after shuffling both
+ * sides) and Sec. 7.2 (each GPU builds a hash table of its local keys).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of a join hash table for m build keys at load factor <= load_factor
+ * (0 < load_factor <= 0.9): a 256-byte header plus 2^L 16-byte slots,
+ * 2^L >= max(64, m / load_factor).  Returns 0 for invalid arguments. */
+size_t gq_join_table_bytes(int64_t m, double load_factor);
+
+/* Build an open-addressing table (linear probing; slot index = top L bits of
+ * fmix64(key)) mapping the unique int64 key[i] to the int32 payload[i], for
+ * i in 0..m-1, or for the rows listed in sel (nullable) of device length
+ * min(*n_dev, m) when n_dev is given.  The table memory (device,
+ * `table_bytes` from gq_join_table_bytes) is fully initialized here.
+ * Device-side errors: GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY (key ==
+ * INT64_MIN, the empty marker), GQ_ERR_CAPACITY.
+ * Host errors: GQ_ERR_INVALID_ARG (table too small for m at load factor 0.9,
+ * NULL pointers, bad m). */
+gq_status gq_join_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, int64_t m,
+                        const int64_t *n_dev, const int32_t *sel,
+                        void *table, size_t table_bytes, gq_stream stream);
+
+/* Workspace for probing at most n rows. */
+size_t gq_join_probe_workspace_bytes(int64_t n);
+
+/* Inner equi-join of probe rows with a built table: for each probe row r
+ * (r = sel[j] for j in 0..len-1, or r = j when sel is NULL), look fk[r] up;
+ * a match emits (prow_out = r, payload_out = payload of the key).  Output
+ * pairs are compacted in probe order; unmatched rows are dropped.
+ *   n, n_dev   host bound / optional device length of the probe (of sel, or
+ *              of fk when sel is NULL)
+ *   prow_out, payload_out  device int32, capacity >= n
+ *   n_out_dev  device int64 scalar, receives the number of pairs
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_WORKSPACE. */
+gq_status gq_join_probe(gq_ctx *ctx, const void *table, const int64_t *fk,
+                        int64_t n, const int64_t *n_dev, const int32_t *sel,
+                        int32_t *prow_out, int32_t *payload_out, int64_t *n_out_dev,
+                        void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Group-by aggregate with exact fixed-point sums (+ float64 finalize)
+ * Paper: Sec. 2.4 (exchange operators are injected before a group-by and for
+ * the final aggregation) and Sec. 2.3 (the final aggregation of partial
+ * results uses a reduction: sum, product, min, max or average).  The paper loads decimals as floating point; here money is an
+ * exact integer in cents and the revenue sum is an exact 128-bit integer.
+ * ------------------------------------------------------------------------ */
+
+/* Input rows of a group-by.  Row j (0 <= j < len) reads its values at row
+ * v = rowid[j] (v = j when rowid is NULL); its key is (key64, key32), each
+ * part read at j or at v as flagged; a NULL key part is 0 for every row.
+ *   revenue(v) = price[v] * (rev_scale - disc[v]) computed in 128 bits. */
+typedef struct gq_groupby_in {
+    int64_t n;                 /* host bound on the number of rows          */
+    const int64_t *n_dev;      /* nullable device length (min with n)       */
+    const int32_t *rowid;      /* nullable device int32[n]                  */
+    const int64_t *key64;      /* nullable device int64                     */
+    int32_t key64_by_rowid;    /* 1: key64[v], 0: key64[j]                  */
+    const int32_t *key32;      /* nullable device int32                     */
+    int32_t key32_by_rowid;    /* 1: key32[v], 0: key32[j]                  */
+    const int64_t *qty;        /* device int64, read at v                   */
+    const int64_t *price;      /* device int64, read at v                   */
+    const int64_t *disc;       /* device int64, read at v                   */
+    int64_t rev_scale;         /* e.g. 100 (percent)                        */
+} gq_groupby_in;
+
+/* Output groups, one entry per distinct key present, in unspecified order.
+ * All arrays are device memory with room for `capacity` groups. */
+typedef struct gq_groups {
+    int64_t *key64;            /* nullable (required if the input has key64) */
+    int32_t *key32;            /* nullable (required if the input has key32) */
+    int64_t *count;            /* number of rows                            */
+    int64_t *sum_qty;          /* sum of qty, wrapping int64                 */
+    uint64_t *sum_rev_lo;      /* low 64 bits of the int128 revenue sum     */
+    int64_t *sum_rev_hi;       /* high 64 bits (two's complement)           */
+    double *avg_qty;           /* (double)sum_qty / (double)count, last      */
+    double *avg_rev;           /* (double)sum_rev / (double)count, last      */
+    int64_t *n_groups;         /* device int64 scalar: number of groups     */
+    int64_t capacity;          /* room in each array                        */
+} gq_groups;
+
+/* Workspace for a group-by of at most n rows into at most max_groups groups.
+ * has_key64 / has_key32 say which key parts the input carries. */
+size_t gq_groupby_workspace_bytes(int64_t n, int64_t max_groups, int has_key64, int has_key32);
+
+/* Aggregate count, sum(qty) and the exact sum of revenue per key, then the
+ * float64 averages (computed last, from the exact integers).  max_groups
+ * sizes the internal tables (it must match the workspace query) and must be
+ * <= out->capacity.
+ * Device-side error: GQ_ERR_CAPACITY when more than max_groups distinct keys
+ * occur.  Host errors: GQ_ERR_INVALID_ARG, GQ_ERR_WORKSPACE. */
+gq_status gq_groupby_agg(gq_ctx *ctx, const gq_groupby_in *in, int64_t max_groups,
+                         const gq_groups *out, void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Top-k
+ * The paper's query plans end by gathering the partial results of every GPU
+ * (Sec. 4.4, whose exchange counts leave that final gather out); a top-k is
+ * the local half of an ORDER BY ... LIMIT k before such a gather.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace for top-k over at most n rows. */
+size_t gq_topk_workspace_bytes(int64_t n, int k);
+
+/* The k selected rows with the largest (descending=1) or smallest
+ * (descending=0) val; equal values are ordered by ascending row id; if fewer
+ * than k rows are selected all of them are returned.  Output sorted.
+ *   val        device int64, indexed by row id
+ *   sel        nullable device int32 row ids (NULL: rows 0..n-1)
+ *   n, n_dev   host bound / optional device length of the selection
+ *   k          1..2048
+ *   val_out    device int64[k], rowid_out device int32[k]
+ *   n_out_dev  device int64 scalar: min(k, selected rows)
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_UNSUPPORTED (k > 2048),
+ * GQ_ERR_WORKSPACE. */
+gq_status gq_topk(gq_ctx *ctx, const int64_t *val, const int32_t *sel, int64_t n,
+                  const int64_t *n_dev, int k, int descending,
+                  int64_t *val_out, int32_t *rowid_out, int64_t *n_out_dev,
+                  void *ws, size_t ws_bytes, gq_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GQ_H */

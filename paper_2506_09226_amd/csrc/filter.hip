@@ -1,0 +1,144 @@
+// Scan + filter: ordered stream compaction of a range predicate.
+//
+// One pass over the column.  A tile of FT_TILE rows is read with coalesced
+// loads (wave w, step c reads rows c*256 + w*64 + lane), each wave's ballot
+// becomes one 64-bit word of a tile bitmap in LDS, each thread then owns 32
+// consecutive rows of the bitmap, a block scan gives in-tile output slots,
+// a decoupled look-back over tiles gives the tile's global offset, and the
+// compacted row ids are staged in LDS and written out contiguously.
+#include "gq_device.h"
+#include "gq_internal.h"
+
+namespace {
+
+constexpr int FT_THREADS = 256;
+constexpr int FT_ITEMS = 32;
+constexpr int FT_TILE = FT_THREADS * FT_ITEMS;     // 8192 rows
+constexpr int FT_WORDS = FT_TILE / 64;              // 128 bitmap words
+
+struct filter_ws {
+    uint32_t *tile_ctr;
+    uint64_t *status;
+};
+
+filter_ws filter_layout(gq_carver &c, int64_t n)
+{
+    filter_ws w;
+    const int64_t tiles = (n + FT_TILE - 1) / FT_TILE;
+    w.tile_ctr = c.take<uint32_t>(64);
+    w.status = c.take<uint64_t>(static_cast<size_t>(tiles > 0 ? tiles : 1));
+    return w;
+}
+
+template <typename T, bool HAS_SEL>
+__global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict__ col,
+                                                            const int32_t *__restrict__ sel_in,
+                                                            int64_t n_bound, const int64_t *n_dev, int64_t lo,
+                                                            int64_t hi, int32_t *__restrict__ out,
+                                                            int64_t *n_out, uint32_t *tile_ctr, uint64_t *status)
+{
+    __shared__ uint64_t bits[FT_WORDS];
+    __shared__ int32_t stage[FT_TILE];
+    __shared__ uint32_t scan_smem[FT_THREADS / 64];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_goff;
+
+    int64_t n = n_bound;
+    if (n_dev) {
+        const int64_t d = *n_dev;
+        n = d < n_bound ? (d > 0 ? d : 0) : n_bound;
+    }
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const int64_t ntiles = (n + FT_TILE - 1) / FT_TILE;
+    if (static_cast<int64_t>(t) >= ntiles) {
+        if (t == 0 && threadIdx.x == 0) *n_out = 0;
+        return;
+    }
+    const int64_t base = static_cast<int64_t>(t) * FT_TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    T v[FT_ITEMS];
+#pragma unroll
+    for (int c = 0; c < FT_ITEMS; ++c) {
+        const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
+        v[c] = 0;
+        if (e < n) v[c] = col[HAS_SEL ? static_cast<int64_t>(sel_in[e]) : e];
+    }
+#pragma unroll
+    for (int c = 0; c < FT_ITEMS; ++c) {
+        const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
+        const int64_t x = static_cast<int64_t>(v[c]);
+        const uint64_t b = gq_ballot(e < n && lo <= x && x < hi);
+        if (lane == 0) bits[c * (FT_THREADS / 64) + wave] = b;
+    }
+    __syncthreads();
+
+    // thread i owns tile rows [32 i, 32 i + 32)
+    uint32_t mine = static_cast<uint32_t>(bits[threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32));
+    uint32_t total;
+    uint32_t pos = gq_block_exclusive_scan<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+    if (wave == 0) {
+        const uint64_t g = gq_lookback(status, t, total);
+        if (lane == 0) s_goff = g;
+    }
+    const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * 32;
+    while (mine) {
+        const int i = __builtin_ctz(mine);
+        mine &= mine - 1;
+        const int64_t e = row0 + i;
+        stage[pos++] = HAS_SEL ? sel_in[e] : static_cast<int32_t>(e);
+    }
+    __syncthreads();
+    const int64_t goff = static_cast<int64_t>(s_goff);
+    for (uint32_t i = threadIdx.x; i < total; i += FT_THREADS) out[goff + i] = stage[i];
+    if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
+}
+
+template <typename T, bool S>
+gq_status launch_filter(gq_ctx *ctx, const void *col, const int32_t *sel_in, int64_t n, const int64_t *n_dev,
+                        int64_t lo, int64_t hi, int32_t *out, int64_t *n_out, filter_ws w, hipStream_t s)
+{
+    const int64_t tiles = (n + FT_TILE - 1) / FT_TILE;
+    const uint32_t grid = static_cast<uint32_t>(tiles > 0 ? tiles : 1);
+    return gq_launch(ctx, "gq_filter", filter_kernel<T, S>, dim3(grid), dim3(FT_THREADS), 0, s,
+                     static_cast<const T *>(col), sel_in, n, n_dev, lo, hi, out, n_out, w.tile_ctr, w.status);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gq_filter_workspace_bytes(int64_t n)
+{
+    if (n < 0) n = 0;
+    gq_carver c(nullptr);
+    filter_layout(c, n);
+    return c.bytes();
+}
+
+gq_status gq_filter(gq_ctx *ctx, const void *col, int dtype, int64_t n, const int64_t *n_dev,
+                    const int32_t *sel_in, int64_t lo, int64_t hi, int32_t *sel_out, int64_t *n_out_dev,
+                    void *ws, size_t ws_bytes, gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if ((!col && n > 0) || !sel_out || !n_out_dev)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter: NULL column, output or count");
+    if (n < 0 || n > GQ_MAX_ROWS) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter: n=%lld out of range", (long long)n);
+    if (dtype != GQ_I32 && dtype != GQ_I64) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter: bad dtype %d", dtype);
+    const size_t need = gq_filter_workspace_bytes(n);
+    if (!ws || ws_bytes < need)
+        return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_filter: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gq_carver c(ws);
+    filter_ws w = filter_layout(c, n);
+    GQ_TRY(gq_zero(ctx, ws, c.off / 4, s));     // tile counter + tile status words
+    if (dtype == GQ_I32)
+        return sel_in ? launch_filter<int32_t, true>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s)
+                      : launch_filter<int32_t, false>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s);
+    return sel_in ? launch_filter<int64_t, true>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s)
+                  : launch_filter<int64_t, false>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s);
+}
+
+}  // extern "C"

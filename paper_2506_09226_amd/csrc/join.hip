@@ -1,0 +1,300 @@
+// Hash equi-join: open-addressing build and ordered probe.
+//
+// Table: a 256-byte header then 2^L slots of 16 bytes {int64 key, int32
+// payload, int32 unused}; EMPTY key = INT64_MIN.  The home slot of a key is
+// the TOP L bits of fmix64(key): the same hash bits that pick a key's radix
+// partition, so a probe stream that was partitioned by that hash touches one
+// contiguous slice of the table at a time.  Linear probing, wrapping.
+//
+// Build: a fill kernel writes header and EMPTY slots; an insert kernel claims
+// slots with a 64-bit compare-and-swap and then stores the payload (the probe
+// runs in a later kernel, so the store is visible to it).
+//
+// Probe: a tile of probe rows is looked up with one 16-byte load per slot
+// visited; matches become a tile bitmap (ballots) and are compacted in probe
+// order exactly like the filter: block scan + decoupled look-back + LDS stage.
+#include "gq_device.h"
+#include "gq_internal.h"
+
+namespace {
+
+constexpr uint64_t JT_MAGIC = 0x6a6f696e74626c31ull;   // "join tbl1"
+constexpr int64_t JT_EMPTY = INT64_MIN;
+constexpr size_t JT_HEADER = 256;
+
+struct jt_header {
+    uint64_t magic;
+    uint32_t log2_slots;
+    uint32_t unused;
+    uint64_t slots;
+};
+
+struct alignas(16) jt_slot {
+    int64_t key;
+    int32_t payload;
+    int32_t unused;
+};
+
+int jt_log2_slots(int64_t m, double lf)
+{
+    double want = static_cast<double>(m) / lf;
+    int L = 6;
+    while (L < 40 && static_cast<double>(1ull << L) < want) ++L;
+    return L;
+}
+
+__global__ void jt_init_kernel(void *table, int log2_slots)
+{
+    const uint64_t slots = 1ull << log2_slots;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        jt_header *h = static_cast<jt_header *>(table);
+        h->magic = JT_MAGIC;
+        h->log2_slots = static_cast<uint32_t>(log2_slots);
+        h->unused = 0;
+        h->slots = slots;
+    }
+    jt_slot *s = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER);
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < slots; i += stride) {
+        jt_slot e;
+        e.key = JT_EMPTY;
+        e.payload = 0;
+        e.unused = 0;
+        s[i] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void jt_insert_kernel(void *table, int log2_slots, const int64_t *__restrict__ key,
+                                                        const int32_t *__restrict__ payload, int64_t m_bound,
+                                                        const int64_t *n_dev, const int32_t *__restrict__ sel,
+                                                        uint32_t *status)
+{
+    int64_t m = m_bound;
+    if (n_dev) {
+        const int64_t d = *n_dev;
+        m = d < m_bound ? (d > 0 ? d : 0) : m_bound;
+    }
+    jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER);
+    const uint64_t mask = (1ull << log2_slots) - 1;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const int64_t r = sel ? static_cast<int64_t>(sel[i]) : i;
+        const int64_t k = key[r];
+        const int32_t p = payload[r];
+        if (k == JT_EMPTY) {
+            gq_raise(status, GQ_ERR_INVALID_KEY);
+            continue;
+        }
+        uint64_t s = gq_fmix64(static_cast<uint64_t>(k)) >> (64 - log2_slots);
+        uint64_t probes = 0;
+        for (; probes <= mask; ++probes) {
+            unsigned long long *kp = reinterpret_cast<unsigned long long *>(&slots[s].key);
+            const unsigned long long prev =
+                atomicCAS(kp, static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
+            if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
+                slots[s].payload = p;
+                break;
+            }
+            if (prev == static_cast<unsigned long long>(k)) {
+                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+        if (probes > mask) gq_raise(status, GQ_ERR_CAPACITY);
+    }
+}
+
+constexpr int JP_THREADS = 256;
+constexpr int JP_ITEMS = 16;
+constexpr int JP_TILE = JP_THREADS * JP_ITEMS;    // 4096 probes
+constexpr int JP_WORDS = JP_TILE / 64;
+
+struct probe_ws {
+    uint32_t *tile_ctr;
+    uint64_t *status;
+};
+
+probe_ws probe_layout(gq_carver &c, int64_t n)
+{
+    probe_ws w;
+    const int64_t tiles = (n + JP_TILE - 1) / JP_TILE;
+    w.tile_ctr = c.take<uint32_t>(64);
+    w.status = c.take<uint64_t>(static_cast<size_t>(tiles > 0 ? tiles : 1));
+    return w;
+}
+
+template <bool HAS_SEL>
+__global__ __launch_bounds__(JP_THREADS) void jt_probe_kernel(const void *table, const int64_t *__restrict__ fk,
+                                                              int64_t n_bound, const int64_t *n_dev,
+                                                              const int32_t *__restrict__ sel,
+                                                              int32_t *__restrict__ prow_out,
+                                                              int32_t *__restrict__ pay_out, int64_t *n_out,
+                                                              uint32_t *tile_ctr, uint64_t *lb_status)
+{
+    __shared__ uint64_t bits[JP_WORDS];
+    __shared__ int32_t pay_elem[JP_TILE];
+    __shared__ int32_t stage_row[JP_TILE];
+    __shared__ int32_t stage_pay[JP_TILE];
+    __shared__ uint32_t scan_smem[JP_THREADS / 64];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_goff;
+
+    int64_t n = n_bound;
+    if (n_dev) {
+        const int64_t d = *n_dev;
+        n = d < n_bound ? (d > 0 ? d : 0) : n_bound;
+    }
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const int64_t ntiles = (n + JP_TILE - 1) / JP_TILE;
+    if (static_cast<int64_t>(t) >= ntiles) {
+        if (t == 0 && threadIdx.x == 0) *n_out = 0;
+        return;
+    }
+    const jt_header *hdr = static_cast<const jt_header *>(table);
+    const int L = static_cast<int>(hdr->log2_slots);
+    const uint64_t mask = (1ull << L) - 1;
+    const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
+    const int64_t base = static_cast<int64_t>(t) * JP_TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    int64_t k[JP_ITEMS];
+#pragma unroll
+    for (int c = 0; c < JP_ITEMS; ++c) {
+        const int64_t e = base + c * JP_THREADS + wave * 64 + lane;
+        k[c] = JT_EMPTY;
+        if (e < n) k[c] = fk[HAS_SEL ? static_cast<int64_t>(sel[e]) : e];
+    }
+    uint64_t s[JP_ITEMS];
+    int4 v[JP_ITEMS];
+#pragma unroll
+    for (int c = 0; c < JP_ITEMS; ++c) {
+        s[c] = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - L);
+        v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
+    }
+#pragma unroll
+    for (int c = 0; c < JP_ITEMS; ++c) {
+        const int64_t e = base + c * JP_THREADS + wave * 64 + lane;
+        bool hit = false;
+        int32_t pay = 0;
+        if (e < n && k[c] != JT_EMPTY) {
+            int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
+            uint64_t probes = 0;
+            while (sk != k[c] && sk != JT_EMPTY && probes < mask) {
+                s[c] = (s[c] + 1) & mask;
+                v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
+                sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
+                ++probes;
+            }
+            hit = sk == k[c];
+            pay = v[c].z;
+        }
+        const int elem = c * JP_THREADS + wave * 64 + lane;
+        pay_elem[elem] = pay;
+        const uint64_t b = gq_ballot(hit);
+        if (lane == 0) bits[c * (JP_THREADS / 64) + wave] = b;
+    }
+    __syncthreads();
+
+    // thread i owns tile elements [16 i, 16 i + 16)
+    uint32_t mine = static_cast<uint32_t>(bits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 16)) & 0xffffu;
+    uint32_t total;
+    uint32_t pos = gq_block_exclusive_scan<JP_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+    if (wave == 0) {
+        const uint64_t g = gq_lookback(lb_status, t, total);
+        if (lane == 0) s_goff = g;
+    }
+    const int elem0 = threadIdx.x * JP_ITEMS;
+    while (mine) {
+        const int i = __builtin_ctz(mine);
+        mine &= mine - 1;
+        const int64_t e = base + elem0 + i;
+        stage_row[pos] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
+        stage_pay[pos] = pay_elem[elem0 + i];
+        ++pos;
+    }
+    __syncthreads();
+    const int64_t goff = static_cast<int64_t>(s_goff);
+    for (uint32_t i = threadIdx.x; i < total; i += JP_THREADS) {
+        prow_out[goff + i] = stage_row[i];
+        pay_out[goff + i] = stage_pay[i];
+    }
+    if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gq_join_table_bytes(int64_t m, double load_factor)
+{
+    if (m < 0 || !(load_factor > 0.0) || load_factor > 0.9) return 0;
+    const int L = jt_log2_slots(m, load_factor);
+    return JT_HEADER + (size_t(1) << L) * sizeof(jt_slot);
+}
+
+gq_status gq_join_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, int64_t m, const int64_t *n_dev,
+                        const int32_t *sel, void *table, size_t table_bytes, gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if (m < 0 || m > GQ_MAX_ROWS) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: m=%lld", (long long)m);
+    if (!table || (m > 0 && (!key || !payload)))
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: NULL key, payload or table");
+    if (reinterpret_cast<uintptr_t>(table) % 256 != 0)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: table must be 256-byte aligned");
+    // largest power-of-two slot count that fits the given bytes
+    if (table_bytes < JT_HEADER + 64 * sizeof(jt_slot))
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: table of %zu bytes is too small", table_bytes);
+    int L = 6;
+    while (L < 40 && JT_HEADER + (size_t(2) << L) * sizeof(jt_slot) <= table_bytes) ++L;
+    if (static_cast<double>(m) > 0.9 * static_cast<double>(1ull << L))
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: %lld keys exceed load factor 0.9 of %llu slots",
+                       (long long)m, (unsigned long long)(1ull << L));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t slots = 1ull << L;
+    uint64_t blocks = (slots + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    GQ_TRY(gq_launch(ctx, "gq_join_init", jt_init_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, table,
+                     L));
+    if (m == 0) return GQ_OK;
+    uint64_t ib = (static_cast<uint64_t>(m) + 255) / 256;
+    if (ib > 65536) ib = 65536;
+    return gq_launch(ctx, "gq_join_build", jt_insert_kernel, dim3(static_cast<uint32_t>(ib)), dim3(256), 0, s, table,
+                     L, key, payload, m, n_dev, sel, ctx->status_dev);
+}
+
+size_t gq_join_probe_workspace_bytes(int64_t n)
+{
+    if (n < 0) n = 0;
+    gq_carver c(nullptr);
+    probe_layout(c, n);
+    return c.bytes();
+}
+
+gq_status gq_join_probe(gq_ctx *ctx, const void *table, const int64_t *fk, int64_t n, const int64_t *n_dev,
+                        const int32_t *sel, int32_t *prow_out, int32_t *payload_out, int64_t *n_out_dev, void *ws,
+                        size_t ws_bytes, gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if (n < 0 || n > GQ_MAX_ROWS) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe: n=%lld", (long long)n);
+    if (!table || (!fk && n > 0) || !prow_out || !payload_out || !n_out_dev)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe: NULL table, fk, output or count");
+    const size_t need = gq_join_probe_workspace_bytes(n);
+    if (!ws || ws_bytes < need)
+        return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_join_probe: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gq_carver c(ws);
+    probe_ws w = probe_layout(c, n);
+    GQ_TRY(gq_zero(ctx, ws, c.off / 4, s));
+    const int64_t tiles = (n + JP_TILE - 1) / JP_TILE;
+    const uint32_t grid = static_cast<uint32_t>(tiles > 0 ? tiles : 1);
+    if (sel)
+        return gq_launch(ctx, "gq_join_probe", jt_probe_kernel<true>, dim3(grid), dim3(JP_THREADS), 0, s, table, fk,
+                         n, n_dev, sel, prow_out, payload_out, n_out_dev, w.tile_ctr, w.status);
+    return gq_launch(ctx, "gq_join_probe", jt_probe_kernel<false>, dim3(grid), dim3(JP_THREADS), 0, s, table, fk, n,
+                     n_dev, sel, prow_out, payload_out, n_out_dev, w.tile_ctr, w.status);
+}
+
+}  // extern "C"

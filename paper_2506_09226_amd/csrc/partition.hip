@@ -1,0 +1,290 @@
+// Radix hash partition (local half of a shuffle), stable.
+//
+//  1. hist:    one LDS histogram per tile of rows -> hist[b * ntiles + t]
+//  2. scan:    device-wide exclusive scan of hist (bucket-major), giving the
+//              output start of every (bucket, tile) run; offsets[b] is the
+//              value at (b, 0).
+//  3. scatter: per tile, each wave ranks its rows inside their bucket with
+//              ballots (stable: rows keep input order), the block turns ranks
+//              into tile-local positions, and every column is staged in LDS in
+//              bucket order and written out as contiguous runs.  Tiles are
+//              mapped so that each XCD works on one contiguous range of tiles,
+//              keeping the partial lines at run boundaries in one L2.
+#include "gq_device.h"
+#include "gq_internal.h"
+#include "gq_ops.h"
+
+namespace {
+
+constexpr int PT_THREADS = 256;
+constexpr int PT_WAVES = PT_THREADS / 64;
+constexpr int PT_MAX_LOG2P = 8;
+constexpr int PT_MAX_COLS = 8;
+
+struct part_cols {
+    const void *in[PT_MAX_COLS];
+    void *out[PT_MAX_COLS];
+    int32_t bytes[PT_MAX_COLS];
+    int32_t n;
+};
+
+template <int LOG2P>
+GQ_DEV uint32_t bucket_of(int64_t key)
+{
+    if constexpr (LOG2P == 0) {
+        (void)key;
+        return 0;
+    } else {
+        return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(key)) >> (64 - LOG2P));
+    }
+}
+
+template <int LOG2P, int ITEMS>
+__global__ __launch_bounds__(PT_THREADS) void part_hist_kernel(const int64_t *__restrict__ key, int64_t n,
+                                                               uint32_t *__restrict__ hist, int64_t ntiles)
+{
+    constexpr int P = 1 << LOG2P;
+    constexpr int TILE = PT_THREADS * ITEMS;
+    __shared__ uint32_t h[P];
+    for (int b = threadIdx.x; b < P; b += PT_THREADS) h[b] = 0;
+    __syncthreads();
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * TILE;
+    int64_t k[ITEMS];
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const int64_t e = base + c * PT_THREADS + threadIdx.x;
+        k[c] = (e < n) ? key[e] : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const int64_t e = base + c * PT_THREADS + threadIdx.x;
+        if (e < n) atomicAdd(&h[bucket_of<LOG2P>(k[c])], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < P; b += PT_THREADS) hist[static_cast<int64_t>(b) * ntiles + blockIdx.x] = h[b];
+}
+
+__global__ void part_offsets_kernel(const uint32_t *__restrict__ scanned, int64_t ntiles, int P, int64_t n,
+                                    int64_t *__restrict__ offsets)
+{
+    for (int b = threadIdx.x; b <= P; b += blockDim.x)
+        offsets[b] = (b < P) ? static_cast<int64_t>(scanned[static_cast<int64_t>(b) * ntiles]) : n;
+}
+
+template <int LOG2P, int ITEMS>
+__global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t *__restrict__ key, int64_t n,
+                                                                  const uint32_t *__restrict__ gofs, int64_t ntiles,
+                                                                  int64_t *__restrict__ key_out,
+                                                                  int32_t *__restrict__ rowid_out, part_cols cols)
+{
+    constexpr int P = 1 << LOG2P;
+    constexpr int TILE = PT_THREADS * ITEMS;
+    constexpr int WROWS = TILE / PT_WAVES;            // rows per wave
+    __shared__ uint32_t wcnt[PT_WAVES][P];            // per-wave running counts, then per-wave prefixes
+    __shared__ uint32_t lstart[P];
+    __shared__ uint32_t gstart[P];
+    __shared__ uint32_t scan_smem[PT_WAVES];
+    __shared__ uint8_t lbucket[TILE];
+    __shared__ uint64_t stage[TILE];
+
+    const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t base = static_cast<int64_t>(tile) * TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < PT_WAVES * P; i += PT_THREADS) (&wcnt[0][0])[i] = 0;
+
+    // rows of this thread: base + wave*WROWS + c*64 + lane (wave-contiguous)
+    const int64_t row0 = base + static_cast<int64_t>(wave) * WROWS + lane;
+    int64_t k[ITEMS];
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const int64_t e = row0 + c * 64;
+        k[c] = (e < n) ? key[e] : 0;
+    }
+    __syncthreads();
+
+    uint32_t pos[ITEMS];     // bucket << 16 | rank in (wave, bucket), then tile-local position
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const bool valid = row0 + c * 64 < n;
+        const uint32_t b = bucket_of<LOG2P>(k[c]);
+        uint64_t match = gq_ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < LOG2P; ++bit) {
+            const bool set = (b >> bit) & 1u;
+            const uint64_t bal = gq_ballot(set);
+            match &= set ? bal : ~bal;
+        }
+        const uint32_t below = gq_mbcnt(match);
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(match));
+        uint32_t old = 0;
+        if (valid) old = wcnt[wave][b];
+        if (valid && below == cnt - 1) wcnt[wave][b] = old + cnt;
+        pos[c] = (b << 16) | (old + below);
+    }
+    __syncthreads();
+
+    // per-bucket totals, per-wave exclusive prefixes, bucket starts in the tile
+    uint32_t tot = 0;
+    for (int b = threadIdx.x; b < P; b += PT_THREADS) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < PT_WAVES; ++w) {
+            const uint32_t x = wcnt[w][b];
+            wcnt[w][b] = run;
+            run += x;
+        }
+        tot = run;                                   // P <= PT_THREADS: one bucket per thread
+    }
+    uint32_t all;
+    const uint32_t excl = gq_block_exclusive_scan<PT_THREADS>(threadIdx.x < P ? tot : 0u, &all, scan_smem);
+    if (threadIdx.x < P) {
+        lstart[threadIdx.x] = excl;
+        gstart[threadIdx.x] = gofs[static_cast<int64_t>(threadIdx.x) * ntiles + tile];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        if (row0 + c * 64 < n) {
+            const uint32_t b = pos[c] >> 16;
+            const uint32_t p = lstart[b] + wcnt[wave][b] + (pos[c] & 0xffffu);
+            lbucket[p] = static_cast<uint8_t>(b);
+            pos[c] = p;
+        }
+    }
+    const int64_t rem = n - base;
+    const uint32_t count = static_cast<uint32_t>(rem < TILE ? rem : TILE);
+
+    // column 0 = key (in registers), 1..ncols = payload columns, last = row id
+    const int ncol_total = 1 + cols.n + (rowid_out ? 1 : 0);
+    for (int ci = 0; ci < ncol_total; ++ci) {
+        const bool is_key = ci == 0;
+        const bool is_rowid = ci == 1 + cols.n;
+        const int width = is_key ? 8 : (is_rowid ? 4 : cols.bytes[ci - 1]);
+        __syncthreads();                              // stage free (and lbucket ready)
+        if (width == 8) {
+            const int64_t *src = is_key ? nullptr : static_cast<const int64_t *>(cols.in[ci - 1]);
+#pragma unroll
+            for (int c = 0; c < ITEMS; ++c) {
+                const int64_t e = row0 + c * 64;
+                if (e < n) stage[pos[c]] = static_cast<uint64_t>(is_key ? k[c] : src[e]);
+            }
+        } else {
+            uint32_t *st32 = reinterpret_cast<uint32_t *>(stage);
+            const int32_t *src = is_rowid ? nullptr : static_cast<const int32_t *>(cols.in[ci - 1]);
+#pragma unroll
+            for (int c = 0; c < ITEMS; ++c) {
+                const int64_t e = row0 + c * 64;
+                if (e < n) st32[pos[c]] = static_cast<uint32_t>(is_rowid ? static_cast<int32_t>(e) : src[e]);
+            }
+        }
+        __syncthreads();
+        if (width == 8) {
+            uint64_t *dst = is_key ? reinterpret_cast<uint64_t *>(key_out) : static_cast<uint64_t *>(cols.out[ci - 1]);
+            for (uint32_t q = threadIdx.x; q < count; q += PT_THREADS) {
+                const uint32_t b = lbucket[q];
+                dst[gstart[b] + (q - lstart[b])] = stage[q];
+            }
+        } else {
+            const uint32_t *st32 = reinterpret_cast<const uint32_t *>(stage);
+            uint32_t *dst = is_rowid ? reinterpret_cast<uint32_t *>(rowid_out) : static_cast<uint32_t *>(cols.out[ci - 1]);
+            for (uint32_t q = threadIdx.x; q < count; q += PT_THREADS) {
+                const uint32_t b = lbucket[q];
+                dst[gstart[b] + (q - lstart[b])] = st32[q];
+            }
+        }
+    }
+}
+
+constexpr int PT_ITEMS = 16;
+constexpr int PT_TILE = PT_THREADS * PT_ITEMS;
+
+struct part_ws {
+    uint32_t *hist;
+    void *scan_ws;
+};
+
+part_ws part_layout(gq_carver &c, int64_t n, int log2p)
+{
+    part_ws w;
+    const int64_t ntiles = n > 0 ? (n + PT_TILE - 1) / PT_TILE : 1;
+    const int64_t cells = ntiles << log2p;
+    w.hist = c.take<uint32_t>(static_cast<size_t>(cells));
+    w.scan_ws = c.take<char>(gq_scan_u32_workspace(cells));
+    return w;
+}
+
+template <int LOG2P>
+gq_status run_partition(gq_ctx *ctx, const int64_t *key, int64_t n, const part_cols &cols, int64_t *key_out,
+                        int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s)
+{
+    constexpr int P = 1 << LOG2P;
+    const int64_t ntiles = n > 0 ? (n + PT_TILE - 1) / PT_TILE : 1;
+    const uint32_t grid = static_cast<uint32_t>(ntiles);
+    GQ_TRY(gq_launch(ctx, "gq_partition_hist", part_hist_kernel<LOG2P, PT_ITEMS>, dim3(grid), dim3(PT_THREADS), 0,
+                     s, key, n, w.hist, ntiles));
+    GQ_TRY(gq_scan_u32(ctx, w.hist, ntiles * P, w.scan_ws, s));
+    GQ_TRY(gq_launch(ctx, "gq_partition_offsets", part_offsets_kernel, dim3(1), dim3(256), 0, s,
+                     static_cast<const uint32_t *>(w.hist), ntiles, P, n, offsets));
+    if (n == 0) return GQ_OK;
+    return gq_launch(ctx, "gq_partition_scatter", part_scatter_kernel<LOG2P, PT_ITEMS>, dim3(grid), dim3(PT_THREADS),
+                     0, s, key, n, static_cast<const uint32_t *>(w.hist), ntiles, key_out, rowid_out, cols);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gq_radix_partition_workspace_bytes(int64_t n, int log2_fanout)
+{
+    if (n < 0) n = 0;
+    if (log2_fanout < 0 || log2_fanout > PT_MAX_LOG2P) return 0;
+    gq_carver c(nullptr);
+    part_layout(c, n, log2_fanout);
+    return c.bytes();
+}
+
+gq_status gq_radix_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log2_fanout, int ncols,
+                             const void *const *cols, const int32_t *col_bytes, int64_t *key_out,
+                             void *const *cols_out, int32_t *rowid_out, int64_t *offsets_dev, void *ws,
+                             size_t ws_bytes, gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if (n < 0 || n > GQ_MAX_ROWS)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_radix_partition: n=%lld out of range", (long long)n);
+    if (!offsets_dev || (n > 0 && (!key || !key_out)))
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_radix_partition: NULL key, key_out or offsets");
+    if (log2_fanout < 0 || log2_fanout > PT_MAX_LOG2P)
+        return gq_fail(ctx, GQ_ERR_UNSUPPORTED, "gq_radix_partition: log2_fanout %d not in [0,%d]", log2_fanout,
+                       PT_MAX_LOG2P);
+    if (ncols < 0 || ncols > PT_MAX_COLS)
+        return gq_fail(ctx, GQ_ERR_UNSUPPORTED, "gq_radix_partition: ncols %d not in [0,%d]", ncols, PT_MAX_COLS);
+    part_cols pc{};
+    pc.n = ncols;
+    for (int i = 0; i < ncols; ++i) {
+        if (!cols || !cols_out || !col_bytes || (n > 0 && (!cols[i] || !cols_out[i])) ||
+            (col_bytes[i] != 4 && col_bytes[i] != 8))
+            return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_radix_partition: bad column %d", i);
+        pc.in[i] = cols[i];
+        pc.out[i] = cols_out[i];
+        pc.bytes[i] = col_bytes[i];
+    }
+    const size_t need = gq_radix_partition_workspace_bytes(n, log2_fanout);
+    if (!ws || ws_bytes < need)
+        return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_radix_partition: workspace %zu < %zu bytes", ws_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gq_carver c(ws);
+    part_ws w = part_layout(c, n, log2_fanout);
+    switch (log2_fanout) {
+    case 0: return run_partition<0>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 1: return run_partition<1>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 2: return run_partition<2>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 3: return run_partition<3>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 4: return run_partition<4>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 5: return run_partition<5>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 6: return run_partition<6>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    case 7: return run_partition<7>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    default: return run_partition<8>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
+    }
+}
+
+}  // extern "C"

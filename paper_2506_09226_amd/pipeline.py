@@ -1,0 +1,78 @@
+"""The plain per-operator form of the hot path: one launch chain per operator.
+
+    partition(fact by fk)  ->  filter(date < date_hi)  ->  join build(dim)
+    ->  probe(partitioned fk via the selection)  ->  group-by(dim attribute)
+    ->  float64 averages  [->  top-k of price over the selection]
+
+All buffers and workspaces are allocated once, so a step allocates nothing and
+never waits for the host: every count travels on the device.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (Context, alloc_groups, gq_filter, gq_groupby_agg, gq_join_build, gq_join_probe,
+               gq_join_table_bytes, gq_radix_partition, gq_topk, lib)
+
+FACT_COLS = ("date", "qty", "price", "disc")
+
+
+class PlainPipeline:
+    def __init__(self, ctx: Context, fact: dict, dim: dict, date_hi: int, max_groups: int,
+                 log2_fanout: int = 6, topk: int = 100, load_factor: float = 0.5, partition: bool = True):
+        self.ctx, self.fact, self.dim = ctx, fact, dim
+        self.date_hi, self.max_groups, self.log2p = date_hi, max_groups, log2_fanout
+        self.k, self.partition = topk, partition
+        d = ctx.device
+        n, m = fact["fk"].numel(), dim["key"].numel()
+        self.n, self.m = n, m
+        L = lib()
+        if partition:
+            self.p_key = torch.empty_like(fact["fk"])
+            self.p_cols = [torch.empty_like(fact[c]) for c in FACT_COLS]
+            self.p_rowid = torch.empty(n, dtype=torch.int32, device=d)
+            self.p_off = torch.empty((1 << log2_fanout) + 1, dtype=torch.int64, device=d)
+            self.ws_part = ctx.workspace(L.gq_radix_partition_workspace_bytes(n, log2_fanout))
+        self.sel = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.n_sel = torch.zeros(1, dtype=torch.int64, device=d)
+        self.ws_filter = ctx.workspace(L.gq_filter_workspace_bytes(n))
+        self.table = torch.empty(gq_join_table_bytes(m, load_factor), dtype=torch.uint8, device=d)
+        self.prow = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.pay = torch.empty(max(n, 1), dtype=torch.int32, device=d)
+        self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
+        self.ws_probe = ctx.workspace(L.gq_join_probe_workspace_bytes(n))
+        self.groups = alloc_groups(ctx, max_groups, False, True)
+        self.ws_gb = ctx.workspace(L.gq_groupby_workspace_bytes(n, max_groups, 0, 1))
+        if topk:
+            self.tk_val = torch.empty(topk, dtype=torch.int64, device=d)
+            self.tk_row = torch.empty(topk, dtype=torch.int32, device=d)
+            self.tk_n = torch.zeros(1, dtype=torch.int64, device=d)
+            self.ws_tk = ctx.workspace(L.gq_topk_workspace_bytes(n, topk))
+
+    def columns(self):
+        """The fact columns the filter/probe/aggregate read (partitioned or not)."""
+        if self.partition:
+            date, qty, price, disc = self.p_cols
+            return self.p_key, date, qty, price, disc
+        f = self.fact
+        return f["fk"], f["date"], f["qty"], f["price"], f["disc"]
+
+    def step(self):
+        ctx, f = self.ctx, self.fact
+        if self.partition:
+            gq_radix_partition(ctx, f["fk"], self.log2p, [f[c] for c in FACT_COLS],
+                               outs=(self.p_key, self.p_cols, self.p_rowid, self.p_off), ws=self.ws_part)
+        fk, date, qty, price, disc = self.columns()
+        gq_filter(ctx, date, -(1 << 31), self.date_hi, out=self.sel, n_out=self.n_sel, ws=self.ws_filter)
+        gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table)
+        gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
+                      payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
+        gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,
+                       max_groups=self.max_groups, out=self.groups, ws=self.ws_gb)
+        if self.k:
+            gq_topk(ctx, price, self.k, sel=self.sel, n=self.n, n_dev=self.n_sel, val_out=self.tk_val,
+                    rowid_out=self.tk_row, n_out=self.tk_n, ws=self.ws_tk)
+
+    def source_rows(self, rows: torch.Tensor) -> torch.Tensor:
+        """Map row ids of the (possibly partitioned) columns to input row ids."""
+        return self.p_rowid[rows.long()] if self.partition else rows

@@ -1,0 +1,356 @@
+"""GPU parity of every operator against the CPU oracle, through the C ABI.
+
+Integers, keys, row ids and 128-bit sums must match bit for bit; float64
+averages within 1e-12 relative.  Sizes span several tiles plus a ragged tail
+(tiles are 4096 or 8192 rows), and the degenerate cases (empty input, no
+match, one group, ties, duplicate and invalid keys) are covered."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2506_09226_amd as gq
+
+pytestmark = pytest.mark.gpu
+
+AVG_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gq.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t, n=None):
+    t = t if n is None else t[:n]
+    return t.cpu().numpy()
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------------ filter ---
+
+@pytest.mark.parametrize("n", [0, 1, 63, 8191, 8192, 8193, 100_003, 1_000_000])
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_filter(ctx, n, dtype):
+    r = rng(n)
+    col = r.integers(0, 2557, size=n).astype(dtype)
+    exp = oracle.filter(col, 100, 1500)
+    out, cnt = gq.gq_filter(ctx, dev(col), 100, 1500)
+    assert ctx.status() == gq.GQ_OK
+    k = int(cnt.item())
+    assert k == len(exp)
+    assert np.array_equal(host(out, k), exp)
+
+
+@pytest.mark.parametrize("n", [5000, 123_457])
+def test_filter_with_selection_and_device_count(ctx, n):
+    r = rng(7)
+    col = r.integers(-1000, 1000, size=n).astype(np.int64)
+    sel_in = np.sort(r.choice(n, size=n // 3, replace=False)).astype(np.int32)
+    used = len(sel_in) - 17                                   # device count below the bound
+    exp = oracle.filter(col, -10, 400, sel_in=sel_in[:used])
+    n_dev = torch.tensor([used], dtype=torch.int64, device="cuda")
+    out, cnt = gq.gq_filter(ctx, dev(col), -10, 400, sel_in=dev(sel_in), n_dev=n_dev)
+    k = int(cnt.item())
+    assert k == len(exp) and np.array_equal(host(out, k), exp)
+
+
+def test_filter_extremes(ctx):
+    col = np.array([-(1 << 63), -1, 0, 1, (1 << 63) - 1] * 3000, dtype=np.int64)
+    for lo, hi in [(-(1 << 63), (1 << 63) - 1), (0, 1), (5, 5), (1, -1)]:
+        exp = oracle.filter(col, lo, hi)
+        out, cnt = gq.gq_filter(ctx, dev(col), lo, hi)
+        k = int(cnt.item())
+        assert np.array_equal(host(out, k), exp)
+
+
+# --------------------------------------------------------------- partition ---
+
+@pytest.mark.parametrize("log2p", [0, 1, 3, 6, 8])
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 70_001])
+def test_partition(ctx, log2p, n):
+    r = rng(n * 10 + log2p)
+    key = r.integers(-(1 << 63), (1 << 63) - 1, size=n, dtype=np.int64)
+    c32 = r.integers(0, 2557, size=n).astype(np.int32)
+    c64 = r.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    ek, (e32, e64), erow, eoff = oracle.partition(key, log2p, [c32, c64])
+    k, (o32, o64), row, off = gq.gq_radix_partition(ctx, dev(key), log2p, [dev(c32), dev(c64)])
+    assert ctx.status() == gq.GQ_OK
+    assert np.array_equal(host(off), eoff)
+    assert np.array_equal(host(k), ek)
+    assert np.array_equal(host(row), erow)
+    assert np.array_equal(host(o32), e32) and np.array_equal(host(o64), e64)
+
+
+def test_partition_skewed_keys(ctx):
+    """Few distinct keys: one bucket gets most rows; order must stay stable."""
+    r = rng(5)
+    key = r.choice(np.array([3, 3, 3, 3, 17, 99, -5], dtype=np.int64), size=50_000)
+    ek, _, erow, eoff = oracle.partition(key, 6)
+    k, _, row, off = gq.gq_radix_partition(ctx, dev(key), 6)
+    assert np.array_equal(host(off), eoff) and np.array_equal(host(row), erow) and np.array_equal(host(k), ek)
+
+
+def test_partition_empty(ctx):
+    k, _, row, off = gq.gq_radix_partition(ctx, torch.empty(0, dtype=torch.int64, device="cuda"), 6)
+    assert host(off).tolist() == [0] * 65
+
+
+def test_partition_rejects_fanout(ctx):
+    with pytest.raises(gq.GQError) as e:
+        gq.gq_radix_partition(ctx, dev(np.zeros(10, np.int64)), 9)
+    assert e.value.code == gq.GQ_ERR_UNSUPPORTED
+
+
+# -------------------------------------------------------------------- join ---
+
+def _dim(m, seed):
+    r = rng(seed)
+    keys = np.unique(r.integers(-(1 << 62), 1 << 62, size=m + m // 10 + 10, dtype=np.int64))
+    keys = r.permutation(keys)[:m]
+    pay = r.integers(0, 1 << 30, size=m).astype(np.int32)
+    return keys, pay
+
+
+@pytest.mark.parametrize("m,n", [(1, 10), (100, 10_000), (65_536, 300_001), (5000, 4096)])
+def test_join_build_probe(ctx, m, n):
+    r = rng(m + n)
+    bkey, bpay = _dim(m, m)
+    fk = np.where(r.random(n) < 0.8, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
+    fk = fk.astype(np.int64)
+    sel = np.sort(r.choice(n, size=n // 2, replace=False)).astype(np.int32)
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay))
+    for s in (None, sel):
+        ep, ey = oracle.join(bkey, bpay, fk, s)
+        prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(fk), sel=None if s is None else dev(s))
+        assert ctx.status() == gq.GQ_OK
+        k = int(cnt.item())
+        assert k == len(ep)
+        assert np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
+
+
+def test_join_high_load_factor_and_device_counts(ctx):
+    r = rng(3)
+    bkey, bpay = _dim(57_000, 3)
+    fk = bkey[r.integers(0, 57_000, size=200_000)]
+    bsel = np.sort(r.choice(57_000, size=50_000, replace=False)).astype(np.int32)
+    n_b = torch.tensor([49_000], dtype=torch.int64, device="cuda")
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), sel=dev(bsel), n_dev=n_b, load_factor=0.9)
+    used_b = bsel[:49_000]
+    psel = np.arange(0, 200_000, 3, dtype=np.int32)
+    n_p = torch.tensor([60_000], dtype=torch.int64, device="cuda")
+    ep, ey = oracle.join(bkey[used_b], bpay[used_b], fk, psel[:60_000])
+    prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(fk), sel=dev(psel), n_dev=n_p)
+    assert ctx.status() == gq.GQ_OK
+    k = int(cnt.item())
+    assert k == len(ep) and np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
+
+
+def test_join_duplicate_and_invalid_keys(ctx):
+    gq.gq_join_build(ctx, dev(np.array([5, 6, 5], np.int64)), dev(np.zeros(3, np.int32)))
+    assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
+    gq.gq_join_build(ctx, dev(np.array([5, -(1 << 63)], np.int64)), dev(np.zeros(2, np.int32)))
+    assert ctx.status() == gq.GQ_ERR_INVALID_KEY
+    assert ctx.status() == gq.GQ_OK                            # cleared by the read
+
+
+def test_join_empty_sides(ctx):
+    table = gq.gq_join_build(ctx, torch.empty(0, dtype=torch.int64, device="cuda"),
+                             torch.empty(0, dtype=torch.int32, device="cuda"))
+    prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(np.arange(1000, dtype=np.int64)))
+    assert int(cnt.item()) == 0
+    prow, pay, cnt = gq.gq_join_probe(ctx, table, torch.empty(0, dtype=torch.int64, device="cuda"))
+    assert int(cnt.item()) == 0
+
+
+# ---------------------------------------------------------------- group-by ---
+
+def _check_groups(res: gq.GroupResult, exp: dict, has64: bool, has32: bool):
+    got = res.host()
+    g = len(got["count"])
+    assert g == len(exp["count"])
+    if has64 and has32:
+        order = np.lexsort((got["key32"], got["key64"]))
+    elif has64:
+        order = np.argsort(got["key64"], kind="stable")
+    elif has32:
+        order = np.argsort(got["key32"], kind="stable")
+    else:
+        order = np.arange(g)
+    for f in ("key64", "key32", "count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
+        if exp[f] is None:
+            continue
+        assert np.array_equal(got[f][order], exp[f]), f
+    for f in ("avg_qty", "avg_rev"):
+        np.testing.assert_allclose(got[f][order], exp[f], rtol=AVG_RTOL, atol=0)
+
+
+def _gb_inputs(n, nv, seed, groups, big=False):
+    r = rng(seed)
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    key32 = r.integers(0, groups, size=n).astype(np.int32)
+    key64 = (r.integers(0, 3, size=nv) * 1_000_000_007 - 7).astype(np.int64)
+    if big:
+        qty = r.integers(1 << 60, 1 << 62, size=nv, dtype=np.int64)
+        price = r.integers((1 << 62) - 1000, 1 << 62, size=nv, dtype=np.int64)
+        price[::5] *= -1
+        disc = r.integers(-50, 11, size=nv).astype(np.int64)
+    else:
+        qty = r.integers(1, 51, size=nv).astype(np.int64)
+        price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+        disc = r.integers(0, 11, size=nv).astype(np.int64)
+    return rowid, key32, key64, qty, price, disc
+
+
+@pytest.mark.parametrize("n,groups", [(1, 1), (4097, 25), (300_000, 25), (200_000, 500), (250_003, 5000),
+                                      (400_000, 150_000)])
+def test_groupby_key32_via_rowid(ctx, n, groups):
+    rowid, key32, _, qty, price, disc = _gb_inputs(n, 2 * n + 1, n + groups, groups)
+    exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                            max_groups=groups)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, True)
+
+
+@pytest.mark.parametrize("max_groups", [64, 4000])
+def test_groupby_composite_key_int128_carry(ctx, max_groups):
+    n = 60_000
+    rowid, key32, key64, qty, price, disc = _gb_inputs(n, n, 11, 7, big=True)
+    exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key64_by_rowid=True, key32=key32)
+    assert any(abs(v) >= 1 << 64 for v in oracle.sum_rev_int(exp))
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                            key64_by_rowid=True, key32=dev(key32), max_groups=max_groups)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, True, True)
+
+
+@pytest.mark.parametrize("max_groups", [16, 100_000])
+def test_groupby_key64_direct_no_rowid(ctx, max_groups):
+    n = 150_000
+    r = rng(21)
+    key64 = r.integers(-(1 << 63), (1 << 63) - 1, size=min(max_groups, 10), dtype=np.int64)[r.integers(0, min(max_groups, 10), size=n)]
+    qty = r.integers(1, 51, size=n).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=n).astype(np.int64)
+    disc = r.integers(0, 11, size=n).astype(np.int64)
+    exp = oracle.groupby(n, qty, price, disc, key64=key64)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), key64=dev(key64), max_groups=max_groups)
+    _check_groups(res, exp, True, False)
+
+
+def test_groupby_no_key_and_empty(ctx):
+    n = 10_000
+    _, _, _, qty, price, disc = _gb_inputs(n, n, 4, 1)
+    exp = oracle.groupby(n, qty, price, disc)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), max_groups=1)
+    _check_groups(res, exp, False, False)
+    n_dev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), n_dev=n_dev, key32=dev(np.zeros(n, np.int32)),
+                            max_groups=4)
+    assert int(res.n_groups.item()) == 0
+
+
+def test_groupby_capacity_error(ctx):
+    n = 5000
+    key32 = np.arange(n, dtype=np.int32)
+    v = np.ones(n, np.int64)
+    gq.gq_groupby_agg(ctx, dev(v), dev(v), dev(v), key32=dev(key32), max_groups=100)
+    assert ctx.status() == gq.GQ_ERR_CAPACITY
+
+
+def _fmix64_np(x):
+    x = x.astype(np.uint64)
+    x ^= x >> np.uint64(33)
+    x *= np.uint64(0xFF51AFD7ED558CCD)
+    x ^= x >> np.uint64(33)
+    x *= np.uint64(0xC4CEB9FE1A85EC53)
+    x ^= x >> np.uint64(33)
+    return x
+
+
+def test_groupby_large_path_overflowing_buckets(ctx):
+    """Thousands of keys that all hash into one bucket overflow that bucket's
+    LDS table: the extra keys go to the global fallback table and the result
+    stays exact."""
+    r = rng(31)
+    cand = r.integers(0, 1 << 31, size=4_000_000).astype(np.int64)
+    with np.errstate(over="ignore"):
+        h = _fmix64_np(cand.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15))
+    hot = np.unique(cand[(h >> np.uint64(57)) == 0])[:9000]          # top 7 bits 0: bucket 0 of 128
+    assert len(hot) == 9000
+    n = 400_000
+    other = r.integers(0, 1 << 31, size=50_000)
+    keys = np.concatenate([hot, other]).astype(np.int32)
+    key32 = keys[r.integers(0, len(keys), size=n)]
+    nv = n
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                            max_groups=250_000)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, True)
+
+
+def test_groupby_repeatable(ctx):
+    """Integer results are identical run to run (no scheduling dependence)."""
+    n = 500_000
+    rowid, key32, _, qty, price, disc = _gb_inputs(n, n, 41, 3000)
+    args = dict(rowid=dev(rowid), key32=dev(key32), max_groups=3000)
+    first = None
+    for _ in range(5):
+        h = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), **args).host()
+        o = np.argsort(h["key32"])
+        cur = [h[f][o] for f in ("key32", "count", "sum_qty", "sum_rev_lo", "sum_rev_hi", "avg_qty", "avg_rev")]
+        if first is None:
+            first = cur
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(first, cur))
+
+
+# ------------------------------------------------------------------- top-k ---
+
+@pytest.mark.parametrize("n,k", [(0, 5), (3, 100), (100, 100), (50_000, 1), (1_000_003, 100), (300_000, 2048)])
+@pytest.mark.parametrize("desc", [True, False])
+def test_topk(ctx, n, k, desc):
+    r = rng(n + k)
+    val = r.integers(-40, 40, size=max(n, 1)).astype(np.int64)     # heavy ties
+    sel = np.sort(r.choice(max(n, 1), size=(n + 1) // 2, replace=False)).astype(np.int32) if n else None
+    ev, er = oracle.topk(val[:n] if n else val[:0], k, sel=sel, descending=desc)
+    v, row, cnt = gq.gq_topk(ctx, dev(val), k, sel=None if sel is None else dev(sel), n=0 if not n else None,
+                             descending=desc)
+    c = int(cnt.item())
+    assert c == len(ev)
+    assert np.array_equal(host(v, c), ev) and np.array_equal(host(row, c), er)
+
+
+def test_topk_ascending_values_adversarial(ctx):
+    """Increasing values in row order raise the threshold at every step."""
+    n = 700_000
+    val = np.arange(n, dtype=np.int64) * 3 - 5
+    ev, er = oracle.topk(val, 100)
+    v, row, cnt = gq.gq_topk(ctx, dev(val), 100)
+    assert np.array_equal(host(v), ev) and np.array_equal(host(row), er)
+
+
+def test_topk_extremes_and_device_count(ctx):
+    val = np.array([-(1 << 63), (1 << 63) - 1, 0, (1 << 63) - 1, -1] * 1000, dtype=np.int64)
+    n_dev = torch.tensor([4003], dtype=torch.int64, device="cuda")
+    ev, er = oracle.topk(val[:4003], 7)
+    v, row, cnt = gq.gq_topk(ctx, dev(val), 7, n_dev=n_dev)
+    assert np.array_equal(host(v), ev) and np.array_equal(host(row), er)
+    with pytest.raises(gq.GQError):
+        gq.gq_topk(ctx, dev(val), 4000)

@@ -1,0 +1,226 @@
+"""GPU parity of the plain per-operator pipeline (the form the benchmark
+times): partition -> filter -> join build/probe -> group-by -> averages ->
+top-k, on the seeded synthetic workloads.
+
+  * small workload (1,048,576 x 65,536, 25 groups) at full size: every stage
+    equals the oracle element by element.
+  * one-GPU share (200M x 25M, ~1.5M groups, 64 buckets) at full size:
+    sampled outputs recomputed row by row (the generator is counter based)
+    and checked by the oracle, plus invariants that hold at any size.
+  * skewed workload (Zipf foreign keys, composite group key) at 1/100 size:
+    element by element.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2506_09226_amd as gq
+from paper_2506_09226_amd.pipeline import FACT_COLS, PlainPipeline
+
+pytestmark = pytest.mark.gpu
+AVG_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gq.Context(0)
+    yield c
+    c.close()
+
+
+def H(t, n=None):
+    return (t if n is None else t[:n]).cpu().numpy()
+
+
+def _sorted_groups(h, by=("key32",)):
+    order = np.lexsort(tuple(h[k] for k in reversed(by)))
+    return {k: (None if v is None else v[order]) for k, v in h.items()}
+
+
+def _assert_groups_equal(got, exp, keys):
+    for f in keys + ("count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
+        assert np.array_equal(got[f], exp[f]), f
+    for f in ("avg_qty", "avg_rev"):
+        np.testing.assert_allclose(got[f], exp[f], rtol=AVG_RTOL, atol=0)
+
+
+def _tables(w, device):
+    fact = synth.fact_table(w.fact, device=device)
+    dim = synth.dim_table(w.dim_m, w.dim_seed, w.attr_range, device=device)
+    return fact, dim
+
+
+def test_small_workload_every_stage(ctx):
+    w = synth.workload(0)
+    fact, dim = _tables(w, "cuda")
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, log2_fanout=w.log2_fanout, topk=100)
+    pl.step()
+    assert ctx.status() == gq.GQ_OK
+    hf = {k: H(v) for k, v in fact.items()}
+    hd = {k: H(v) for k, v in dim.items()}
+    # partition
+    ek, ecols, erow, eoff = oracle.partition(hf["fk"], w.log2_fanout, [hf[c] for c in FACT_COLS])
+    assert np.array_equal(H(pl.p_off), eoff)
+    assert np.array_equal(H(pl.p_key), ek) and np.array_equal(H(pl.p_rowid), erow)
+    for got, exp in zip(pl.p_cols, ecols):
+        assert np.array_equal(H(got), exp)
+    pdate, pqty, pprice, pdisc = ecols
+    # filter
+    esel = oracle.filter(pdate, -(1 << 31), w.date_hi)
+    ns = int(pl.n_sel.item())
+    assert ns == len(esel) and np.array_equal(H(pl.sel, ns), esel)
+    # join
+    eprow, epay = oracle.join(hd["key"], hd["attr"], ek, esel)
+    nj = int(pl.n_join.item())
+    assert nj == len(eprow) == ns
+    assert np.array_equal(H(pl.prow, nj), eprow) and np.array_equal(H(pl.pay, nj), epay)
+    # group-by + averages
+    eg = oracle.groupby(nj, pqty, pprice, pdisc, rowid=eprow, key32=epay)
+    got = _sorted_groups(pl.groups.host())
+    _assert_groups_equal(got, eg, ("key32",))
+    # top-k
+    ev, er = oracle.topk(pprice, 100, sel=esel)
+    assert np.array_equal(H(pl.tk_val), ev) and np.array_equal(H(pl.tk_row), er)
+
+
+def test_small_workload_partitioning_does_not_change_the_join(ctx):
+    """The join/aggregate result is the same whether or not the fact table was
+    partitioned first (the paper's join strategies agree)."""
+    w = synth.workload(0)
+    fact, dim = _tables(w, "cuda")
+    res = []
+    for part in (True, False):
+        pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, partition=part, topk=0)
+        pl.step()
+        res.append(_sorted_groups(pl.groups.host()))
+    _assert_groups_equal(res[0], res[1], ("key32",))
+
+
+def test_pipeline_repeated_steps_identical(ctx):
+    w = synth.workload(0, scale=0.25)
+    fact, dim = _tables(w, "cuda")
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, topk=100)
+    outs = []
+    for _ in range(3):
+        pl.step()
+        outs.append((_sorted_groups(pl.groups.host()), H(pl.tk_row).copy(), H(pl.p_key).copy()))
+    for o in outs[1:]:
+        _assert_groups_equal(o[0], outs[0][0], ("key32",))
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+
+
+def test_skewed_workload_reduced(ctx):
+    w = synth.workload(2, scale=0.01)           # 1M fact rows, Zipf FKs over 100K dim rows
+    fact, dim = _tables(w, "cuda")
+    hf = {k: H(v) for k, v in fact.items()}
+    hd = {k: H(v) for k, v in dim.items()}
+    # (i) group-by over all rows on the composite key (fk, g32)
+    n = w.fact.n
+    eg = oracle.groupby(n, hf["qty"], hf["price"], hf["disc"], key64=hf["fk"], key32=hf["g32"])
+    res = gq.gq_groupby_agg(ctx, fact["qty"], fact["price"], fact["disc"], key64=fact["fk"], key32=fact["g32"],
+                            max_groups=len(eg["count"]) + 1000)
+    assert ctx.status() == gq.GQ_OK
+    _assert_groups_equal(_sorted_groups(res.host(), ("key64", "key32")), eg, ("key64", "key32"))
+    # (ii) filter(5%) -> join -> group-by on the composite key
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, partition=False, topk=100)
+    pl.step()
+    esel = oracle.filter(hf["date"], -(1 << 31), w.date_hi)
+    eprow, epay = oracle.join(hd["key"], hd["attr"], hf["fk"], esel)
+    nj = int(pl.n_join.item())
+    assert np.array_equal(H(pl.prow, nj), eprow) and np.array_equal(H(pl.pay, nj), epay)
+    eg2 = oracle.groupby(nj, hf["qty"], hf["price"], hf["disc"], rowid=eprow, key64=hf["fk"], key64_by_rowid=True,
+                         key32=hf["g32"], key32_by_rowid=True)
+    res2 = gq.gq_groupby_agg(ctx, fact["qty"], fact["price"], fact["disc"], n=nj, rowid=pl.prow,
+                             key64=fact["fk"], key64_by_rowid=True, key32=fact["g32"], key32_by_rowid=True,
+                             max_groups=len(eg2["count"]) + 10)
+    _assert_groups_equal(_sorted_groups(res2.host(), ("key64", "key32")), eg2, ("key64", "key32"))
+    ev, er = oracle.topk(hf["price"], 100, sel=esel)
+    assert np.array_equal(H(pl.tk_val), ev) and np.array_equal(H(pl.tk_row), er)
+
+
+def test_one_gpu_share_full_size_sampled(ctx):
+    """200M fact rows, 25M dim rows, 64 buckets, ~1.5M groups: the benchmark's
+    launch configuration, checked on sampled outputs and invariants."""
+    w = synth.workload(1)
+    fact, dim = _tables(w, "cuda")
+    n, m = w.fact.n, w.dim_m
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=6, topk=100)
+    pl.step()
+    torch.cuda.synchronize()
+    assert ctx.status() == gq.GQ_OK
+    rs = np.random.default_rng(1234)
+
+    # partition: offsets, permutation, stability, sampled rows and buckets
+    off = H(pl.p_off)
+    assert off[0] == 0 and off[-1] == n and np.all(np.diff(off) >= 0)
+    cnt = np.diff(off)
+    assert abs(cnt.mean() - n / 64) < 1 and cnt.min() > n / 64 * 0.99       # uniform hash
+    rowid = pl.p_rowid
+    assert torch.equal(torch.sort(rowid)[0], torch.arange(n, dtype=torch.int32, device="cuda"))
+    inc = (rowid[1:] > rowid[:-1])
+    boundary = torch.zeros(n - 1, dtype=torch.bool, device="cuda")
+    bpos = torch.from_numpy(off[1:-1] - 1).cuda()
+    boundary[bpos[bpos < n - 1]] = True
+    assert bool((inc | boundary).all())
+    q = np.sort(rs.integers(0, n, size=20_000))
+    qs = torch.from_numpy(q).cuda()
+    src = H(rowid[qs]).astype(np.int64)
+    cols = synth.fact_columns(w.fact, torch.from_numpy(src))
+    assert np.array_equal(H(pl.p_key[qs]), cols["fk"].numpy())
+    for name, got in zip(FACT_COLS, pl.p_cols):
+        assert np.array_equal(H(got[qs]), cols[name].numpy()), name
+    bucket_of_q = np.searchsorted(off, q, side="right") - 1
+    for qi, b, k in zip(q[:2000], bucket_of_q[:2000], H(pl.p_key[qs[:2000]])):
+        assert oracle.fmix64(int(k)) >> 58 == b
+
+    # filter: ascending, exact count, every selected row passes
+    pdate = pl.p_cols[0]
+    ns = int(pl.n_sel.item())
+    assert ns == int((pdate < w.date_hi).sum().item())
+    sel = pl.sel[:ns]
+    assert bool((sel[1:] > sel[:-1]).all()) and bool((pdate[sel.long()] < w.date_hi).all())
+
+    # join: every foreign key references a dim key -> |join| = |sel|, rows = selection
+    nj = int(pl.n_join.item())
+    assert nj == ns and torch.equal(pl.prow[:nj], sel)
+    i = np.sort(rs.integers(0, nj, size=20_000))
+    it = torch.from_numpy(i).cuda()
+    src = H(rowid[pl.prow[it].long()]).astype(np.int64)
+    u = synth.uniform_int(w.fact.seed, synth.S_FK_ROW, torch.from_numpy(src), 0, m - 1)
+    attr = synth.dim_columns(w.dim_seed, u, w.attr_range)["attr"].numpy()
+    assert np.array_equal(H(pl.pay[it]), attr)
+
+    # group-by: totals and sampled groups recomputed by the oracle
+    g = pl.groups.host()
+    ng = len(g["count"])
+    assert 0.99 * w.attr_range < ng <= w.attr_range
+    assert int(g["count"].sum()) == nj
+    prow = pl.prow[:nj].long()
+    _, pqty, pprice, pdisc = pl.p_cols
+    assert int(g["sum_qty"].sum()) == int(pqty[prow].sum().item())
+    rev_total = int((pprice[prow] * (100 - pdisc[prow])).sum().item())
+    assert np.all(g["sum_rev_hi"] == 0) and sum(int(x) for x in g["sum_rev_lo"]) == rev_total
+    pick = rs.choice(ng, size=4, replace=False)
+    pay = pl.pay[:nj]
+    for gi in pick:
+        key = int(g["key32"][gi])
+        rows = prow[pay == key]
+        qv, pv, dv = H(pqty[rows]), H(pprice[rows]), H(pdisc[rows])
+        e = oracle.groupby(len(qv), qv, pv, dv)
+        assert g["count"][gi] == e["count"][0] and g["sum_qty"][gi] == e["sum_qty"][0]
+        assert g["sum_rev_lo"][gi] == e["sum_rev_lo"][0] and g["sum_rev_hi"][gi] == e["sum_rev_hi"][0]
+        np.testing.assert_allclose([g["avg_qty"][gi], g["avg_rev"][gi]], [e["avg_qty"][0], e["avg_rev"][0]],
+                                   rtol=AVG_RTOL, atol=0)
+
+    # top-k: the oracle over every selected row whose price reaches the k-th value
+    v, r = H(pl.tk_val), H(pl.tk_row)
+    t = int(v[-1])
+    psel = pprice[sel.long()]
+    cand = sel[psel >= t]
+    assert int((psel > t).sum().item()) < 100 <= cand.numel()
+    ev, er = oracle.topk(H(pprice), 100, sel=H(cand))
+    assert np.array_equal(v, ev) and np.array_equal(r, er)
