@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16_777_216)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (3 times) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU exchange is not built",
@@ -134,6 +136,13 @@ def main():
     w = synth.workload(args.workload)
     torch.cuda.set_device(0)
     ctx = gq.Context(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     fact = synth.fact_table(w.fact, device="cuda")
     dim = synth.dim_table(w.dim_m, w.dim_seed, w.attr_range, device="cuda")
