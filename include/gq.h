@@ -164,18 +164,24 @@ gq_status gq_radix_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log
  * 2^L >= max(64, m / load_factor).  Returns 0 for invalid arguments. */
 size_t gq_join_table_bytes(int64_t m, double load_factor);
 
+/* Workspace for gq_join_build of m keys into a table of table_bytes bytes
+ * (a few hundred bytes for small tables; about 26 bytes per key for the
+ * region build of large tables). */
+size_t gq_join_build_workspace_bytes(int64_t m, size_t table_bytes);
+
 /* Build an open-addressing table (linear probing; slot index = top L bits of
  * fmix64(key)) mapping the unique int64 key[i] to the int32 payload[i], for
  * i in 0..m-1, or for the rows listed in sel (nullable) of device length
  * min(*n_dev, m) when n_dev is given.  The table memory (device,
- * `table_bytes` from gq_join_table_bytes) is fully initialized here.
+ * `table_bytes` from gq_join_table_bytes, 256-byte aligned) is fully
+ * initialized here; its slot count is the largest power of two that fits.
  * Device-side errors: GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY (key ==
  * INT64_MIN, the empty marker), GQ_ERR_CAPACITY.
  * Host errors: GQ_ERR_INVALID_ARG (table too small for m at load factor 0.9,
- * NULL pointers, bad m). */
+ * NULL pointers, bad m), GQ_ERR_WORKSPACE. */
 gq_status gq_join_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, int64_t m,
                         const int64_t *n_dev, const int32_t *sel,
-                        void *table, size_t table_bytes, gq_stream stream);
+                        void *table, size_t table_bytes, void *ws, size_t ws_bytes, gq_stream stream);
 
 /* Workspace for probing at most n rows. */
 size_t gq_join_probe_workspace_bytes(int64_t n);
@@ -273,6 +279,62 @@ gq_status gq_topk(gq_ctx *ctx, const int64_t *val, const int32_t *sel, int64_t n
                   const int64_t *n_dev, int k, int descending,
                   int64_t *val_out, int32_t *rowid_out, int64_t *n_out_dev,
                   void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched join + aggregate: many independent instances in one persistent
+ * launch.  Each instance is the filter -> join -> group-by -> averages
+ * pipeline above on its own tables (the per-GPU body of the engine run on
+ * many small queries at once).
+ * ------------------------------------------------------------------------ */
+
+typedef struct gq_instance {
+    const int64_t *dim_key;    /* device int64[m], unique                   */
+    const int32_t *dim_attr;   /* device int32[m], the group key            */
+    int64_t m;
+    const int64_t *fk;         /* device fact columns, n rows each          */
+    const int32_t *date;
+    const int64_t *qty, *price, *disc;
+    int64_t n;
+    int64_t date_lo, date_hi;  /* filter date_lo <= date < date_hi          */
+    int64_t rev_scale;         /* revenue = price * (rev_scale - disc)      */
+    gq_groups out;             /* key32 required; capacity >= groups, <= 2^24 */
+} gq_instance;
+
+typedef struct gq_tuning {
+    double load_factor;        /* hash-table load factor (0, 0.9]           */
+    int32_t probe_tile;        /* fact rows per probe work item (multiple of 4096) */
+    int32_t build_tile;        /* keys per build work item (multiple of 256) */
+    int32_t init_tile;         /* slots per table-fill work item            */
+    int32_t lag;               /* probe items of instance i follow the build
+                                  items of instance i + lag in the queue    */
+} gq_tuning;
+
+/* Defaults: load factor 0.5, 8192-row probe tiles, 4096-key build tiles,
+ * 16384-slot fill tiles, lag 2. */
+gq_tuning gq_default_tuning(void);
+
+/* Workspace for gq_batch_join_agg (0 for invalid arguments).  It holds every
+ * instance's hash table and group table. */
+size_t gq_batch_workspace_bytes(const gq_instance *inst, int n_inst, const gq_tuning *tuning);
+
+/* Run every instance of the host array inst[0..n_inst) in one persistent
+ * kernel; tuning NULL = gq_default_tuning().  Each instance's out receives its
+ * groups (unordered) and n_groups, exactly as gq_groupby_agg would.  ws must be
+ * 256-byte aligned.  Device-side errors: GQ_ERR_DUPLICATE_KEY,
+ * GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY.  Host errors: GQ_ERR_INVALID_ARG,
+ * GQ_ERR_WORKSPACE. */
+gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, const gq_tuning *tuning,
+                            void *ws, size_t ws_bytes, gq_stream stream);
+
+/* Autotuner: times every candidate tuning (load factor x probe tile x lag) on
+ * the given instances and returns the fastest in *best (its time in
+ * *best_ms).  cache_path (nullable) names a text file: a tuning already stored
+ * for the same instance sizes is returned without timing; a new result is
+ * appended.  Synchronizes the stream.  ws must hold
+ * gq_batch_autotune_workspace_bytes(inst, n_inst). */
+size_t gq_batch_autotune_workspace_bytes(const gq_instance *inst, int n_inst);
+gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, const char *cache_path,
+                            gq_tuning *best, double *best_ms, void *ws, size_t ws_bytes, gq_stream stream);
 
 #ifdef __cplusplus
 }

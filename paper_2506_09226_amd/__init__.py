@@ -34,8 +34,10 @@ GQ_I32, GQ_I64 = 4, 8
 EXPORTED = [
     "gq_ctx_create", "gq_ctx_destroy", "gq_last_error", "gq_status_word", "gq_set_timing", "gq_kernel_time",
     "gq_reset_timing", "gq_filter_workspace_bytes", "gq_filter", "gq_radix_partition_workspace_bytes",
-    "gq_radix_partition", "gq_join_table_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
+    "gq_radix_partition", "gq_join_table_bytes", "gq_join_build_workspace_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
     "gq_join_probe", "gq_groupby_workspace_bytes", "gq_groupby_agg", "gq_topk_workspace_bytes", "gq_topk",
+    "gq_default_tuning", "gq_batch_workspace_bytes", "gq_batch_join_agg", "gq_batch_autotune_workspace_bytes",
+    "gq_batch_autotune",
 ]
 
 
@@ -56,6 +58,21 @@ class Groups(C.Structure):
     _fields_ = [("key64", C.c_void_p), ("key32", C.c_void_p), ("count", C.c_void_p), ("sum_qty", C.c_void_p),
                 ("sum_rev_lo", C.c_void_p), ("sum_rev_hi", C.c_void_p), ("avg_qty", C.c_void_p),
                 ("avg_rev", C.c_void_p), ("n_groups", C.c_void_p), ("capacity", C.c_int64)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("dim_key", C.c_void_p), ("dim_attr", C.c_void_p), ("m", C.c_int64),
+                ("fk", C.c_void_p), ("date", C.c_void_p), ("qty", C.c_void_p), ("price", C.c_void_p),
+                ("disc", C.c_void_p), ("n", C.c_int64), ("date_lo", C.c_int64), ("date_hi", C.c_int64),
+                ("rev_scale", C.c_int64), ("out", Groups)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("load_factor", C.c_double), ("probe_tile", C.c_int32), ("build_tile", C.c_int32),
+                ("init_tile", C.c_int32), ("lag", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -93,8 +110,10 @@ def lib():
         L.gq_radix_partition.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.gq_join_table_bytes.restype = sz
         L.gq_join_table_bytes.argtypes = [i64, C.c_double]
+        L.gq_join_build_workspace_bytes.restype = sz
+        L.gq_join_build_workspace_bytes.argtypes = [i64, sz]
         L.gq_join_build.restype = st
-        L.gq_join_build.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
+        L.gq_join_build.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp, sz, vp]
         L.gq_join_probe_workspace_bytes.restype = sz
         L.gq_join_probe_workspace_bytes.argtypes = [i64]
         L.gq_join_probe.restype = st
@@ -107,6 +126,17 @@ def lib():
         L.gq_topk_workspace_bytes.argtypes = [i64, i32]
         L.gq_topk.restype = st
         L.gq_topk.argtypes = [vp, vp, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
+        L.gq_default_tuning.restype = Tuning
+        L.gq_default_tuning.argtypes = []
+        L.gq_batch_workspace_bytes.restype = sz
+        L.gq_batch_workspace_bytes.argtypes = [C.POINTER(Instance), i32, C.POINTER(Tuning)]
+        L.gq_batch_join_agg.restype = st
+        L.gq_batch_join_agg.argtypes = [vp, C.POINTER(Instance), i32, C.POINTER(Tuning), vp, sz, vp]
+        L.gq_batch_autotune_workspace_bytes.restype = sz
+        L.gq_batch_autotune_workspace_bytes.argtypes = [C.POINTER(Instance), i32]
+        L.gq_batch_autotune.restype = st
+        L.gq_batch_autotune.argtypes = [vp, C.POINTER(Instance), i32, C.c_char_p, C.POINTER(Tuning),
+                                        C.POINTER(C.c_double), vp, sz, vp]
         _lib = L
     return _lib
 
@@ -225,14 +255,16 @@ def gq_join_table_bytes(m: int, load_factor: float = 0.5) -> int:
 
 
 def gq_join_build(ctx: Context, key, payload, m: int | None = None, n_dev=None, sel=None, table=None,
-                  load_factor: float = 0.5):
+                  load_factor: float = 0.5, ws=None):
     """Build the join hash table; returns the table tensor (device bytes)."""
     if m is None:
         m = sel.numel() if sel is not None else key.numel()
     if table is None:
         table = torch.empty(gq_join_table_bytes(m, load_factor), dtype=torch.uint8, device=ctx.device)
+    if ws is None:
+        ws = ctx.workspace(lib().gq_join_build_workspace_bytes(m, table.numel()))
     ctx.check(lib().gq_join_build(ctx.handle, _ptr(key), _ptr(payload), m, _ptr(n_dev), _ptr(sel), _ptr(table),
-                                  table.numel(), _stream(ctx.device)))
+                                  table.numel(), _ptr(ws), ws.numel(), _stream(ctx.device)))
     return table
 
 
@@ -314,3 +346,47 @@ def gq_topk(ctx: Context, val, k: int, sel=None, n: int | None = None, n_dev=Non
     ctx.check(lib().gq_topk(ctx.handle, _ptr(val), _ptr(sel), n, _ptr(n_dev), k, int(descending), _ptr(val_out),
                             _ptr(rowid_out), _ptr(n_out), _ptr(ws), ws.numel(), _stream(ctx.device)))
     return val_out, rowid_out, n_out
+
+
+def _groups_struct(g: GroupResult) -> Groups:
+    return Groups(_ptr(g.key64), _ptr(g.key32), _ptr(g.count), _ptr(g.sum_qty), _ptr(g.sum_rev_lo),
+                  _ptr(g.sum_rev_hi), _ptr(g.avg_qty), _ptr(g.avg_rev), _ptr(g.n_groups), g.count.numel())
+
+
+def make_instances(specs) -> "C.Array":
+    """specs: dicts with dim_key, dim_attr, fk, date, qty, price, disc (tensors),
+    date_lo, date_hi, rev_scale and out (GroupResult with key32)."""
+    arr = (Instance * len(specs))()
+    for i, sp in enumerate(specs):
+        arr[i] = Instance(_ptr(sp["dim_key"]), _ptr(sp["dim_attr"]), sp["dim_key"].numel(),
+                          _ptr(sp["fk"]), _ptr(sp["date"]), _ptr(sp["qty"]), _ptr(sp["price"]), _ptr(sp["disc"]),
+                          sp["fk"].numel(), sp["date_lo"], sp["date_hi"], sp.get("rev_scale", 100),
+                          _groups_struct(sp["out"]))
+    return arr
+
+
+def gq_default_tuning() -> Tuning:
+    return lib().gq_default_tuning()
+
+
+def gq_batch_join_agg(ctx: Context, instances, tuning: Tuning | None = None, ws=None):
+    """Run all instances (a ctypes Instance array) in one persistent launch."""
+    n = len(instances)
+    tp = C.byref(tuning) if tuning is not None else None
+    need = lib().gq_batch_workspace_bytes(instances, n, tp)
+    if need == 0:
+        raise GQError(GQ_ERR_INVALID_ARG, "invalid batch or tuning")
+    ws = ws if ws is not None else ctx.workspace(need)
+    ctx.check(lib().gq_batch_join_agg(ctx.handle, instances, n, tp, _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return ws
+
+
+def gq_batch_autotune(ctx: Context, instances, cache_path: str | None = None, ws=None):
+    """Fastest candidate tuning for these instances; returns (Tuning, ms)."""
+    n = len(instances)
+    need = lib().gq_batch_autotune_workspace_bytes(instances, n)
+    ws = ws if ws is not None else ctx.workspace(need)
+    best, ms = Tuning(), C.c_double()
+    ctx.check(lib().gq_batch_autotune(ctx.handle, instances, n, cache_path.encode() if cache_path else None,
+                                      C.byref(best), C.byref(ms), _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return best, ms.value

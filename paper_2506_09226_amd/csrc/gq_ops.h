@@ -6,4 +6,22 @@
 // In-place exclusive scan of n uint32 values (n >= 0); ws must hold
 // gq_scan_u32_workspace(n) bytes and is zeroed by the call.
 size_t gq_scan_u32_workspace(int64_t n);
-gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStream_t s);
+gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStream_t s, const char *name);
+
+// Stable partition of n rows by the log2p (0..8) bits of fmix64(key) that
+// start at bit `shift` (no row ids).  ws: gq_partition_bits_workspace(n, log2p).
+size_t gq_partition_bits_workspace(int64_t n, int log2p);
+// Kernel names of one use of the partition (for per-kernel timing).
+struct gq_part_names {
+    const char *hist, *scan, *offsets, *scatter;
+};
+gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, int ncols,
+                            void *const *cols, const int32_t *col_bytes, int64_t *key_out, void *const *cols_out,
+                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &names);
+
+// In place: per-tile bucket counts cnt[t*P + b] (tile-major) become the output
+// offsets of each (tile, bucket) run; start[0..P] receives the bucket starts
+// (start[P] = total).  P <= 1024.  ws: gq_tile_offsets_workspace(ntiles, P).
+size_t gq_tile_offsets_workspace(int64_t ntiles, int P);
+gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
+                          hipStream_t s, const char *name);

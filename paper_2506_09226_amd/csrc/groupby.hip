@@ -23,6 +23,8 @@
 // retries the same slot on its next pass of a wave-uniform loop, so the
 // claiming lane always finishes first.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "gq_device.h"
 #include "gq_internal.h"
@@ -301,6 +303,53 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 }
 
 // -------------------------------------------------------------- large path
+//
+// Partitioned rows are AoS records of 32 bytes (key64 or key32, qty, price,
+// disc) or 64 bytes (composite key), written whole from registers: every
+// record covers whole 32-byte memory sectors, so scattered short runs cost no
+// partial-sector write amplification and need no LDS staging.
+// A record is stored and loaded as whole 16-byte vectors (padding included),
+// so each 32-byte sector is written completely by one store pair.
+template <bool K64, bool K32>
+struct gb_rec {
+    static constexpr int VECS = (K64 && K32) ? 4 : 2;   // 16-byte vectors per record
+    uint4 v[VECS];
+};
+
+template <bool K64, bool K32>
+GQ_DEV gb_rec<K64, K32> make_rec(int64_t k64, int32_t k32, int64_t qty, int64_t price, int64_t disc)
+{
+    gb_rec<K64, K32> r;
+    const uint64_t kw = K64 ? static_cast<uint64_t>(k64) : static_cast<uint64_t>(static_cast<uint32_t>(k32));
+    r.v[0] = make_uint4(static_cast<uint32_t>(kw), static_cast<uint32_t>(kw >> 32), static_cast<uint32_t>(qty),
+                        static_cast<uint32_t>(static_cast<uint64_t>(qty) >> 32));
+    r.v[1] = make_uint4(static_cast<uint32_t>(price), static_cast<uint32_t>(static_cast<uint64_t>(price) >> 32),
+                        static_cast<uint32_t>(disc), static_cast<uint32_t>(static_cast<uint64_t>(disc) >> 32));
+    if constexpr (K64 && K32) {
+        r.v[2] = make_uint4(static_cast<uint32_t>(k32), 0u, 0u, 0u);
+        r.v[3] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    return r;
+}
+
+GQ_DEV int64_t u64_of(uint32_t lo, uint32_t hi)
+{
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+template <bool K64, bool K32>
+GQ_DEV void read_rec(const gb_rec<K64, K32> *recs, int64_t i, int64_t &k64, int32_t &k32, int64_t &qty,
+                     int64_t &price, int64_t &disc)
+{
+    const uint4 *p = reinterpret_cast<const uint4 *>(recs + i);
+    const uint4 a = p[0], b = p[1];
+    k64 = K64 ? u64_of(a.x, a.y) : 0;
+    k32 = K32 ? static_cast<int32_t>(K64 ? p[2].x : a.x) : 0;
+    qty = u64_of(a.z, a.w);
+    price = u64_of(b.x, b.y);
+    disc = u64_of(b.z, b.w);
+}
+
 template <bool K64, bool K32>
 GQ_DEV void load_key(const gb_args &a, int64_t j, int64_t &k64, int32_t &k32)
 {
@@ -310,18 +359,19 @@ GQ_DEV void load_key(const gb_args &a, int64_t j, int64_t &k64, int32_t &k32)
     k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
 }
 
+// LDS histogram of one tile of rows, written as the tile's row hist[t * P + b].
 template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int log2p, uint32_t *__restrict__ hist,
-                                                             int64_t ntiles)
+__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int log2p, int items,
+                                                             uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[1 << GB_MAX_LOG2P];
     const int P = 1 << log2p;
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) h[b] = 0;
+    for (int i = threadIdx.x; i < P; i += GB_THREADS) h[i] = 0;
     __syncthreads();
     const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * GB_TILE;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * GB_THREADS * items;
 #pragma unroll 4
-    for (int c = 0; c < GB_ITEMS; ++c) {
+    for (int c = 0; c < items; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
         if (j < n) {
             int64_t k64;
@@ -331,66 +381,103 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int log2
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) hist[static_cast<int64_t>(b) * ntiles + blockIdx.x] = h[b];
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) hist[static_cast<int64_t>(blockIdx.x) * P + b] = h[b];
 }
 
-struct gb_part {
-    int64_t *k64;
-    int32_t *k32;
-    int64_t *qty;
-    int64_t *price;
-    int64_t *disc;
-};
-
+// Scatter rows to their buckets: rank inside (bucket, tile) by an LDS atomic
+// (order inside a bucket is irrelevant to sums), then write each record whole
+// to gofs[b, t] + rank.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int log2p,
                                                                 const uint32_t *__restrict__ gofs, int64_t ntiles,
-                                                                gb_part p)
+                                                                gb_rec<K64, K32> *__restrict__ recs)
 {
     constexpr int PMAX = 1 << GB_MAX_LOG2P;
     __shared__ uint32_t lcnt[PMAX];
-    __shared__ uint32_t lstart[PMAX];
     __shared__ uint32_t gstart[PMAX];
-    __shared__ uint32_t scan_smem[GB_THREADS / 64];
-    __shared__ uint16_t lbucket[GB_TILE];
-    __shared__ uint64_t stage[GB_TILE];
-
     const int P = 1 << log2p;
     const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
     const int64_t n = eff_n(a.n_bound, a.n_dev);
     const int64_t base = static_cast<int64_t>(tile) * GB_TILE;
     if (base >= n) return;                          // whole block: uniform
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) lcnt[b] = 0;
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) {
+        lcnt[b] = 0;
+        gstart[b] = gofs[static_cast<int64_t>(tile) * P + b];
+    }
     __syncthreads();
-
-    int64_t k64[GB_ITEMS], qty[GB_ITEMS], price[GB_ITEMS], disc[GB_ITEMS];
-    int32_t k32[GB_ITEMS];
-    uint32_t pos[GB_ITEMS];
+    gb_rec<K64, K32> r[GB_ITEMS];
+    uint32_t dst[GB_ITEMS];
 #pragma unroll
     for (int c = 0; c < GB_ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        k64[c] = 0;
-        k32[c] = 0;
-        qty[c] = price[c] = disc[c] = 0;
         if (j < n) {
             const int64_t v = a.rowid ? static_cast<int64_t>(a.rowid[j]) : j;
-            if (K64) k64[c] = a.key64[a.key64_by_rowid ? v : j];
-            if (K32) k32[c] = a.key32[a.key32_by_rowid ? v : j];
-            qty[c] = a.qty[v];
-            price[c] = a.price[v];
-            disc[c] = a.disc[v];
+            int64_t k64 = 0;
+            int32_t k32 = 0;
+            if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
+            if (K32) k32 = a.key32[a.key32_by_rowid ? v : j];
+            r[c] = make_rec<K64, K32>(k64, k32, a.qty[v], a.price[v], a.disc[v]);
+            const uint32_t b = static_cast<uint32_t>(gb_hash(k64, k32) >> (64 - log2p));
+            dst[c] = (b << 20) | atomicAdd(&lcnt[b], 1u);
         }
     }
+    __syncthreads();
 #pragma unroll
     for (int c = 0; c < GB_ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
         if (j < n) {
-            const uint32_t b = static_cast<uint32_t>(gb_hash(k64[c], k32[c]) >> (64 - log2p));
+            const uint32_t b = dst[c] >> 20;
+            uint4 *d = reinterpret_cast<uint4 *>(recs + static_cast<int64_t>(gstart[b]) + (dst[c] & 0xfffffu));
+#pragma unroll
+            for (int q = 0; q < gb_rec<K64, K32>::VECS; ++q) d[q] = r[c].v[q];
+        }
+    }
+}
+
+// Staged variant: records are placed in LDS in bucket order and written out
+// as contiguous runs (consecutive threads store consecutive 16-byte vectors).
+constexpr int GB_STAGED_ITEMS = 8;                  // 2048-row tiles: 64 KiB of 32-byte records
+
+template <bool K64, bool K32>
+__global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a, int log2p,
+                                                                       const uint32_t *__restrict__ gofs,
+                                                                       int64_t ntiles,
+                                                                       gb_rec<K64, K32> *__restrict__ recs)
+{
+    constexpr int PMAX = 1 << GB_MAX_LOG2P;
+    constexpr int ITEMS = (K64 && K32) ? GB_STAGED_ITEMS / 2 : GB_STAGED_ITEMS;
+    constexpr int TILE = GB_THREADS * ITEMS;
+    constexpr int VECS = gb_rec<K64, K32>::VECS;
+    __shared__ uint32_t lcnt[PMAX];
+    __shared__ uint32_t lstart[PMAX];
+    __shared__ uint32_t gstart[PMAX];
+    __shared__ uint32_t scan_smem[GB_THREADS / 64];
+    __shared__ uint16_t lbucket[TILE];
+    __shared__ uint4 stage[TILE * VECS];
+    const int P = 1 << log2p;
+    const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t n = eff_n(a.n_bound, a.n_dev);
+    const int64_t base = static_cast<int64_t>(tile) * TILE;
+    if (base >= n) return;                          // whole block: uniform
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) lcnt[b] = 0;
+    __syncthreads();
+    gb_rec<K64, K32> r[ITEMS];
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const int64_t j = base + c * GB_THREADS + threadIdx.x;
+        if (j < n) {
+            const int64_t v = a.rowid ? static_cast<int64_t>(a.rowid[j]) : j;
+            int64_t k64 = 0;
+            int32_t k32 = 0;
+            if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
+            if (K32) k32 = a.key32[a.key32_by_rowid ? v : j];
+            r[c] = make_rec<K64, K32>(k64, k32, a.qty[v], a.price[v], a.disc[v]);
+            const uint32_t b = static_cast<uint32_t>(gb_hash(k64, k32) >> (64 - log2p));
             pos[c] = (b << 16) | atomicAdd(&lcnt[b], 1u);
         }
     }
     __syncthreads();
-    // exclusive scan of lcnt over P buckets: each thread owns P/256 (>= 1) consecutive buckets
     const int per = (P + GB_THREADS - 1) / GB_THREADS;
     uint32_t local = 0;
     for (int i = 0; i < per; ++i) {
@@ -404,55 +491,47 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int l
         if (b < P) {
             lstart[b] = run;
             run += lcnt[b];
-            gstart[b] = gofs[static_cast<int64_t>(b) * ntiles + tile];
+            gstart[b] = gofs[static_cast<int64_t>(tile) * P + b];
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < GB_ITEMS; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
         if (j < n) {
             const uint32_t b = pos[c] >> 16;
             const uint32_t q = lstart[b] + (pos[c] & 0xffffu);
             lbucket[q] = static_cast<uint16_t>(b);
-            pos[c] = q;
+#pragma unroll
+            for (int x = 0; x < VECS; ++x) stage[q * VECS + x] = r[c].v[x];
         }
     }
+    __syncthreads();
     const int64_t rem = n - base;
-    const uint32_t count = static_cast<uint32_t>(rem < GB_TILE ? rem : GB_TILE);
-    // columns: 0 k64, 1 k32, 2 qty, 3 price, 4 disc
-    for (int col = 0; col < 5; ++col) {
-        if ((col == 0 && !K64) || (col == 1 && !K32)) continue;
-        __syncthreads();
-        if (col == 1) {
-            uint32_t *st32 = reinterpret_cast<uint32_t *>(stage);
-#pragma unroll
-            for (int c = 0; c < GB_ITEMS; ++c)
-                if (base + c * GB_THREADS + threadIdx.x < n) st32[pos[c]] = static_cast<uint32_t>(k32[c]);
-        } else {
-#pragma unroll
-            for (int c = 0; c < GB_ITEMS; ++c) {
-                if (base + c * GB_THREADS + threadIdx.x < n) {
-                    const int64_t x = col == 0 ? k64[c] : (col == 2 ? qty[c] : (col == 3 ? price[c] : disc[c]));
-                    stage[pos[c]] = static_cast<uint64_t>(x);
-                }
-            }
-        }
-        __syncthreads();
-        if (col == 1) {
-            const uint32_t *st32 = reinterpret_cast<const uint32_t *>(stage);
-            for (uint32_t q = threadIdx.x; q < count; q += GB_THREADS) {
-                const uint32_t b = lbucket[q];
-                p.k32[gstart[b] + (q - lstart[b])] = static_cast<int32_t>(st32[q]);
-            }
-        } else {
-            int64_t *dst = col == 0 ? p.k64 : (col == 2 ? p.qty : (col == 3 ? p.price : p.disc));
-            for (uint32_t q = threadIdx.x; q < count; q += GB_THREADS) {
-                const uint32_t b = lbucket[q];
-                dst[gstart[b] + (q - lstart[b])] = static_cast<int64_t>(stage[q]);
-            }
-        }
+    const uint32_t count = static_cast<uint32_t>(rem < TILE ? rem : TILE);
+    uint4 *out = reinterpret_cast<uint4 *>(recs);
+    for (uint32_t e = threadIdx.x; e < count * VECS; e += GB_THREADS) {
+        const uint32_t q = e / VECS, x = e % VECS;
+        const uint32_t b = lbucket[q];
+        out[(static_cast<int64_t>(gstart[b]) + (q - lstart[b])) * VECS + x] = stage[e];
     }
+}
+
+// Which scatter: "direct" (records written from registers) or "staged" (LDS,
+// contiguous runs).  GQ_GROUPBY_SCATTER overrides the default.
+bool gb_staged()
+{
+    static const bool v = [] {
+        const char *e = getenv("GQ_GROUPBY_SCATTER");
+        return !(e && strcmp(e, "direct") == 0);
+    }();
+    return v;
+}
+
+int gb_items(bool k64, bool k32)
+{
+    if (!gb_staged()) return GB_ITEMS;
+    return (k64 && k32) ? GB_STAGED_ITEMS / 2 : GB_STAGED_ITEMS;
 }
 
 template <bool K64, bool K32>
@@ -461,20 +540,17 @@ struct bucket_slots {
 };
 
 template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(gb_part p, const uint32_t *__restrict__ gofs,
-                                                                      int64_t ntiles, int log2p, int64_t n_bound,
-                                                                      const int64_t *n_dev, int64_t rev_scale,
+__global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const gb_rec<K64, K32> *__restrict__ recs,
+                                                                      const uint32_t *__restrict__ start,
+                                                                      int64_t rev_scale,
                                                                       gtable g, gq_groups out, uint32_t *status)
 {
     constexpr int SLOTS = bucket_slots<K64, K32>::value;
     __shared__ lds_table<SLOTS, K64, K32> T;
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     __shared__ unsigned long long s_base;
-    const int P = 1 << log2p;
     const int b = static_cast<int>(blockIdx.x);
-    const int64_t n = eff_n(n_bound, n_dev);
-    const int64_t r0 = gofs[static_cast<int64_t>(b) * ntiles];
-    const int64_t r1 = (b + 1 < P) ? static_cast<int64_t>(gofs[static_cast<int64_t>(b + 1) * ntiles]) : n;
+    const int64_t r0 = start[b], r1 = start[b + 1];
     lds_init(T);
     __syncthreads();
     for (int64_t i0 = r0; i0 < r1; i0 += GB_BUCKET_THREADS) {
@@ -484,10 +560,9 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(gb_part p,
         int32_t k32 = 0;
         gq_i128 rev{0, 0};
         if (active) {
-            if (K64) k64 = p.k64[i];
-            if (K32) k32 = p.k32[i];
-            q = p.qty[i];
-            rev = gq_revenue(p.price[i], rev_scale, p.disc[i]);
+            int64_t price, disc;
+            read_rec<K64, K32>(recs, i, k64, k32, q, price, disc);
+            rev = gq_revenue(price, rev_scale, disc);
         }
         const uint64_t h = gb_hash(k64, k32);
         const int s = lds_find(T, active, h, k64, k32);
@@ -532,16 +607,19 @@ uint64_t next_pow2(uint64_t x)
 struct gb_plan {
     bool small;
     int log2p;
+    int items;              // rows per thread of a hist/scatter tile
     int64_t ntiles;
     uint64_t gslots;
 };
 
-gb_plan make_plan(int64_t n, int64_t max_groups, bool k64)
+gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
 {
     gb_plan pl{};
     pl.small = max_groups <= GB_SMALL_GROUPS;
     pl.gslots = next_pow2(static_cast<uint64_t>(max_groups > 32 ? 2 * max_groups : 64));
-    pl.ntiles = n > 0 ? (n + GB_TILE - 1) / GB_TILE : 1;
+    pl.items = gb_items(k64, k32);
+    const int64_t tile = static_cast<int64_t>(GB_THREADS) * pl.items;
+    pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
     if (!pl.small) {
         const int64_t per_bucket = (k64 ? 3072 : 4096) / 2;
         const uint64_t want = static_cast<uint64_t>((max_groups + per_bucket - 1) / per_bucket);
@@ -555,8 +633,9 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64)
 struct gb_ws {
     gtable g;
     uint32_t *hist;
+    uint32_t *start;
     void *scan_ws;
-    gb_part part;
+    void *recs;             // partitioned rows, 32- or 64-byte records
     size_t zero_bytes;      // prefix of the workspace to clear (the table)
 };
 
@@ -576,13 +655,10 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     if (!pl.small) {
         const int64_t cells = pl.ntiles << pl.log2p;
         w.hist = c.take<uint32_t>(static_cast<size_t>(cells));
-        w.scan_ws = c.take<char>(gq_scan_u32_workspace(cells));
+        w.start = c.take<uint32_t>((size_t(1) << pl.log2p) + 1);
+        w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, 1 << pl.log2p));
         const size_t rows = static_cast<size_t>(n > 0 ? n : 1);
-        w.part.k64 = c.take<int64_t>(k64 ? rows : 1);
-        w.part.k32 = c.take<int32_t>(k32 ? rows : 1);
-        w.part.qty = c.take<int64_t>(rows);
-        w.part.price = c.take<int64_t>(rows);
-        w.part.disc = c.take<int64_t>(rows);
+        w.recs = c.take<char>(rows * ((k64 && k32) ? 64 : 32));
     }
     return w;
 }
@@ -604,14 +680,20 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                          w.g, out, ctx->status_dev);
     }
     const uint32_t grid = static_cast<uint32_t>(pl.ntiles);
+    const int P = 1 << pl.log2p;
     GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a,
-                     pl.log2p, w.hist, pl.ntiles));
-    GQ_TRY(gq_scan_u32(ctx, w.hist, pl.ntiles << pl.log2p, w.scan_ws, s));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a,
-                     pl.log2p, static_cast<const uint32_t *>(w.hist), pl.ntiles, w.part));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(1u << pl.log2p),
-                     dim3(GB_BUCKET_THREADS), 0, s, w.part, static_cast<const uint32_t *>(w.hist), pl.ntiles,
-                     pl.log2p, a.n_bound, a.n_dev, a.rev_scale, w.g, out, ctx->status_dev));
+                     pl.log2p, pl.items, w.hist));
+    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, P, w.start, w.scan_ws, s, "gq_groupby_scan"));
+    auto *recs = static_cast<gb_rec<K64, K32> *>(w.recs);
+    if (pl.items == GB_ITEMS)
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s,
+                         a, pl.log2p, static_cast<const uint32_t *>(w.hist), pl.ntiles, recs));
+    else
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_staged_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS),
+                         0, s, a, pl.log2p, static_cast<const uint32_t *>(w.hist), pl.ntiles, recs));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(P)),
+                     dim3(GB_BUCKET_THREADS), 0, s, static_cast<const gb_rec<K64, K32> *>(recs),
+                     static_cast<const uint32_t *>(w.start), a.rev_scale, w.g, out, ctx->status_dev));
     return gq_launch(ctx, "gq_groupby_emit", gb_table_emit_kernel<K64, K32>, dim3(emit_blocks), dim3(256), 0, s, w.g,
                      out, ctx->status_dev);
 }
@@ -624,7 +706,7 @@ size_t gq_groupby_workspace_bytes(int64_t n, int64_t max_groups, int has_key64, 
 {
     if (n < 0) n = 0;
     if (max_groups < 1) max_groups = 1;
-    gb_plan pl = make_plan(n, max_groups, has_key64 != 0);
+    gb_plan pl = make_plan(n, max_groups, has_key64 != 0, has_key32 != 0);
     gq_carver c(nullptr);
     gb_layout(c, pl, n, has_key64 != 0, has_key32 != 0);
     return c.bytes();
@@ -650,7 +732,7 @@ gq_status gq_groupby_agg(gq_ctx *ctx, const gq_groupby_in *in, int64_t max_group
     if (!ws || ws_bytes < need)
         return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_groupby_agg: workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    gb_plan pl = make_plan(n, max_groups, k64);
+    gb_plan pl = make_plan(n, max_groups, k64, k32);
     gq_carver c(ws);
     gb_ws w = gb_layout(c, pl, n, k64, k32);
     GQ_TRY(gq_zero(ctx, ws, w.zero_bytes / 4, s));

@@ -6,15 +6,29 @@
 // partition, so a probe stream that was partitioned by that hash touches one
 // contiguous slice of the table at a time.  Linear probing, wrapping.
 //
-// Build: a fill kernel writes header and EMPTY slots; an insert kernel claims
-// slots with a 64-bit compare-and-swap and then stores the payload (the probe
-// runs in a later kernel, so the store is visible to it).
+// Build, small tables: a fill kernel writes header and EMPTY slots; an insert
+// kernel claims slots with a 64-bit compare-and-swap in device memory and then
+// stores the payload (the probe runs in a later kernel, so it sees the store).
+//
+// Build, large tables (device-memory CAS runs at only ~10 G/s on MI355X): the
+// build rows are radix-partitioned (stable LSD passes of the partition
+// operator) by the region of their home slot, a region being 4096 consecutive
+// slots; one workgroup per region inserts its keys into an LDS copy of the
+// region with LDS compare-and-swap and writes the region out linearly.  A key
+// whose probe runs past its region's last slot goes to an overflow list and is
+// inserted afterwards by device CAS from the first slot of the next region,
+// which is exactly where linear probing would continue; the table is the same
+// valid linear-probing table either way.
 //
 // Probe: a tile of probe rows is looked up with one 16-byte load per slot
 // visited; matches become a tile bitmap (ballots) and are compacted in probe
 // order exactly like the filter: block scan + decoupled look-back + LDS stage.
+#include <cstdlib>
+#include <cstring>
+
 #include "gq_device.h"
 #include "gq_internal.h"
+#include "gq_ops.h"
 
 namespace {
 
@@ -103,6 +117,209 @@ __global__ __launch_bounds__(256) void jt_insert_kernel(void *table, int log2_sl
         }
         if (probes > mask) gq_raise(status, GQ_ERR_CAPACITY);
     }
+}
+
+constexpr int JR_BITS = 12;                         // 4096 slots per region (64 KiB)
+constexpr int JR_SLOTS = 1 << JR_BITS;
+constexpr int JR_MAX_REGION_BITS = 16;              // two 8-bit partition passes at most
+constexpr int64_t JR_MIN_KEYS = 1 << 18;            // below this the CAS build is used
+
+// Start offset of every region in the region-sorted keys: roff[r] = first i
+// with region(keys[i]) >= r, roff[2^g] = m.  Each entry is written once, by
+// the element at which the region sequence steps past it.
+__global__ __launch_bounds__(256) void jt_region_bounds_kernel(const int64_t *__restrict__ keys, int64_t m, int g,
+                                                               int64_t *__restrict__ roff)
+{
+    const int64_t nr = int64_t(1) << g;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= m;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t prev =
+            i == 0 ? -1 : static_cast<int64_t>(gq_fmix64(static_cast<uint64_t>(keys[i - 1])) >> (64 - g));
+        const int64_t cur = i == m ? nr : static_cast<int64_t>(gq_fmix64(static_cast<uint64_t>(keys[i])) >> (64 - g));
+        for (int64_t r = prev + 1; r <= cur; ++r) roff[r] = i;
+    }
+}
+
+__global__ __launch_bounds__(256) void jt_region_kernel(void *table, int L, const int64_t *__restrict__ keys,
+                                                        const int32_t *__restrict__ pay,
+                                                        const int64_t *__restrict__ roff,
+                                                        int64_t *__restrict__ ovf_key, int32_t *__restrict__ ovf_pay,
+                                                        uint32_t *ovf_cnt, int64_t ovf_cap, uint32_t *status)
+{
+    __shared__ unsigned long long sk[JR_SLOTS];
+    __shared__ int32_t sp[JR_SLOTS];
+    const uint64_t region = blockIdx.x;
+    for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+        sk[j] = static_cast<unsigned long long>(JT_EMPTY);
+        sp[j] = 0;
+    }
+    __syncthreads();
+    const int64_t r0 = roff[region], r1 = roff[region + 1];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const int64_t k = keys[i];
+        const int32_t p = pay[i];
+        if (k == JT_EMPTY) {
+            gq_raise(status, GQ_ERR_INVALID_KEY);
+            continue;
+        }
+        uint32_t loc = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k)) >> (64 - L)) & (JR_SLOTS - 1);
+        while (true) {
+            const unsigned long long prev =
+                atomicCAS(&sk[loc], static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
+            if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
+                sp[loc] = p;
+                break;
+            }
+            if (prev == static_cast<unsigned long long>(k)) {
+                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                break;
+            }
+            if (++loc == JR_SLOTS) {                 // continue in the next region, later
+                const uint32_t idx = atomicAdd(ovf_cnt, 1u);
+                if (idx < ovf_cap) {
+                    ovf_key[idx] = k;
+                    ovf_pay[idx] = p;
+                } else {
+                    gq_raise(status, GQ_ERR_CAPACITY);
+                }
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        jt_header *h = static_cast<jt_header *>(table);
+        h->magic = JT_MAGIC;
+        h->log2_slots = static_cast<uint32_t>(L);
+        h->unused = 0;
+        h->slots = 1ull << L;
+    }
+    jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER) + (region << JR_BITS);
+    for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+        jt_slot e;
+        e.key = static_cast<int64_t>(sk[j]);
+        e.payload = sp[j];
+        e.unused = 0;
+        slots[j] = e;
+    }
+}
+
+__global__ __launch_bounds__(256) void jt_overflow_kernel(void *table, int L, const int64_t *__restrict__ ovf_key,
+                                                          const int32_t *__restrict__ ovf_pay,
+                                                          const uint32_t *ovf_cnt, int64_t ovf_cap, uint32_t *status)
+{
+    const int64_t cnt = *ovf_cnt;
+    const int64_t n = cnt < ovf_cap ? cnt : ovf_cap;
+    jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER);
+    const uint64_t mask = (1ull << L) - 1;
+    const int g = L - JR_BITS;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t k = ovf_key[i];
+        const uint64_t home_region = gq_fmix64(static_cast<uint64_t>(k)) >> (64 - g);
+        uint64_t s = ((home_region + 1) << JR_BITS) & mask;
+        uint64_t probes = 0;
+        for (; probes <= mask; ++probes) {
+            unsigned long long *kp = reinterpret_cast<unsigned long long *>(&slots[s].key);
+            const unsigned long long prev =
+                atomicCAS(kp, static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
+            if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
+                slots[s].payload = ovf_pay[i];
+                break;
+            }
+            if (prev == static_cast<unsigned long long>(k)) {
+                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+        if (probes > mask) gq_raise(status, GQ_ERR_CAPACITY);
+    }
+}
+
+int table_log2_from_bytes(size_t table_bytes)
+{
+    int L = 6;
+    while (L < 40 && JT_HEADER + (size_t(2) << L) * sizeof(jt_slot) <= table_bytes) ++L;
+    return L;
+}
+
+// Which build a call takes: "region" for large tables built from whole
+// columns, "cas" otherwise.  GQ_JOIN_BUILD=cas|region forces one (testing).
+bool use_region_build(int64_t m, int L, bool has_sel_or_count)
+{
+    const int g = L - JR_BITS;
+    if (has_sel_or_count || g < 1 || g > JR_MAX_REGION_BITS) return false;
+    const char *e = getenv("GQ_JOIN_BUILD");
+    if (e && strcmp(e, "cas") == 0) return false;
+    if (e && strcmp(e, "region") == 0) return true;
+    return m >= JR_MIN_KEYS;
+}
+
+struct build_ws {
+    int64_t *k1, *k2;
+    int32_t *p1, *p2;
+    int64_t *offsets;
+    int64_t *roff;
+    void *part_ws;
+    int64_t *ovf_key;
+    int32_t *ovf_pay;
+    uint32_t *ovf_cnt;
+    int64_t ovf_cap;
+};
+
+build_ws build_layout(gq_carver &c, int64_t m)
+{
+    build_ws w{};
+    const size_t rows = static_cast<size_t>(m > 0 ? m : 1);
+    w.ovf_cnt = c.take<uint32_t>(64);
+    w.k1 = c.take<int64_t>(rows);
+    w.k2 = c.take<int64_t>(rows);
+    w.p1 = c.take<int32_t>(rows);
+    w.p2 = c.take<int32_t>(rows);
+    w.offsets = c.take<int64_t>(257);
+    w.roff = c.take<int64_t>((size_t(1) << JR_MAX_REGION_BITS) + 1);
+    w.part_ws = c.take<char>(gq_partition_bits_workspace(m, 8));
+    w.ovf_cap = m / 8 + 1024;
+    w.ovf_key = c.take<int64_t>(static_cast<size_t>(w.ovf_cap));
+    w.ovf_pay = c.take<int32_t>(static_cast<size_t>(w.ovf_cap));
+    return w;
+}
+
+gq_status region_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, int64_t m, void *table, int L,
+                       void *ws, hipStream_t s)
+{
+    gq_carver c(ws);
+    build_ws w = build_layout(c, m);
+    const int g = L - JR_BITS;
+    const int32_t pbytes = 4;
+    static const gq_part_names nm{"gq_join_build_part_hist", "gq_join_build_part_scan", "gq_join_build_part_offsets",
+                                  "gq_join_build_part_scatter"};
+    GQ_TRY(gq_zero(ctx, w.ovf_cnt, 64, s));
+    if (g <= 8) {
+        void *in[1] = {const_cast<int32_t *>(payload)};
+        void *out[1] = {w.p2};
+        GQ_TRY(gq_partition_bits(ctx, key, m, g, 64 - g, 1, in, &pbytes, w.k2, out, w.offsets, w.part_ws, s, nm));
+    } else {                                        // LSD: low digit first, both passes stable
+        const int d1 = g / 2, d2 = g - d1;
+        void *in1[1] = {const_cast<int32_t *>(payload)};
+        void *out1[1] = {w.p1};
+        GQ_TRY(gq_partition_bits(ctx, key, m, d1, 64 - g, 1, in1, &pbytes, w.k1, out1, w.offsets, w.part_ws, s, nm));
+        void *in2[1] = {w.p1};
+        void *out2[1] = {w.p2};
+        GQ_TRY(gq_partition_bits(ctx, w.k1, m, d2, 64 - d2, 1, in2, &pbytes, w.k2, out2, w.offsets, w.part_ws, s, nm));
+    }
+    uint64_t bb = (static_cast<uint64_t>(m) + 256) / 256;
+    if (bb > 8192) bb = 8192;
+    GQ_TRY(gq_launch(ctx, "gq_join_build_bounds", jt_region_bounds_kernel, dim3(static_cast<uint32_t>(bb)), dim3(256),
+                     0, s, static_cast<const int64_t *>(w.k2), m, g, w.roff));
+    GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(1u << g), dim3(256), 0, s, table, L,
+                     static_cast<const int64_t *>(w.k2), static_cast<const int32_t *>(w.p2),
+                     static_cast<const int64_t *>(w.roff), w.ovf_key, w.ovf_pay, w.ovf_cnt, w.ovf_cap,
+                     ctx->status_dev));
+    return gq_launch(ctx, "gq_join_build_overflow", jt_overflow_kernel, dim3(64), dim3(256), 0, s, table, L,
+                     static_cast<const int64_t *>(w.ovf_key), static_cast<const int32_t *>(w.ovf_pay),
+                     static_cast<const uint32_t *>(w.ovf_cnt), w.ovf_cap, ctx->status_dev);
 }
 
 constexpr int JP_THREADS = 256;
@@ -235,8 +452,19 @@ size_t gq_join_table_bytes(int64_t m, double load_factor)
     return JT_HEADER + (size_t(1) << L) * sizeof(jt_slot);
 }
 
+size_t gq_join_build_workspace_bytes(int64_t m, size_t table_bytes)
+{
+    if (m < 0) m = 0;
+    const int L = table_log2_from_bytes(table_bytes);
+    if (!use_region_build(m, L, false)) return 256;
+    gq_carver c(nullptr);
+    build_layout(c, m);
+    return c.bytes();
+}
+
 gq_status gq_join_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, int64_t m, const int64_t *n_dev,
-                        const int32_t *sel, void *table, size_t table_bytes, gq_stream stream)
+                        const int32_t *sel, void *table, size_t table_bytes, void *ws, size_t ws_bytes,
+                        gq_stream stream)
 {
     if (!ctx) return GQ_ERR_INVALID_ARG;
     if (m < 0 || m > GQ_MAX_ROWS) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: m=%lld", (long long)m);
@@ -244,24 +472,27 @@ gq_status gq_join_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload,
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: NULL key, payload or table");
     if (reinterpret_cast<uintptr_t>(table) % 256 != 0)
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: table must be 256-byte aligned");
-    // largest power-of-two slot count that fits the given bytes
     if (table_bytes < JT_HEADER + 64 * sizeof(jt_slot))
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: table of %zu bytes is too small", table_bytes);
-    int L = 6;
-    while (L < 40 && JT_HEADER + (size_t(2) << L) * sizeof(jt_slot) <= table_bytes) ++L;
+    const int L = table_log2_from_bytes(table_bytes);
     if (static_cast<double>(m) > 0.9 * static_cast<double>(1ull << L))
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_build: %lld keys exceed load factor 0.9 of %llu slots",
                        (long long)m, (unsigned long long)(1ull << L));
+    const bool region = use_region_build(m, L, sel != nullptr || n_dev != nullptr);
+    const size_t need = gq_join_build_workspace_bytes(m, table_bytes);
+    if (region && (!ws || ws_bytes < need))
+        return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_join_build: workspace %zu < %zu bytes", ws_bytes, need);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (region) return region_build(ctx, key, payload, m, table, L, ws, s);
     const uint64_t slots = 1ull << L;
     uint64_t blocks = (slots + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    GQ_TRY(gq_launch(ctx, "gq_join_init", jt_init_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, table,
+    GQ_TRY(gq_launch(ctx, "gq_join_build_init", jt_init_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, table,
                      L));
     if (m == 0) return GQ_OK;
     uint64_t ib = (static_cast<uint64_t>(m) + 255) / 256;
     if (ib > 65536) ib = 65536;
-    return gq_launch(ctx, "gq_join_build", jt_insert_kernel, dim3(static_cast<uint32_t>(ib)), dim3(256), 0, s, table,
+    return gq_launch(ctx, "gq_join_build_insert", jt_insert_kernel, dim3(static_cast<uint32_t>(ib)), dim3(256), 0, s, table,
                      L, key, payload, m, n_dev, sel, ctx->status_dev);
 }
 

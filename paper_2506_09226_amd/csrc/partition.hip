@@ -1,15 +1,17 @@
 // Radix hash partition (local half of a shuffle), stable.
 //
-//  1. hist:    one LDS histogram per tile of rows -> hist[b * ntiles + t]
-//  2. scan:    device-wide exclusive scan of hist (bucket-major), giving the
-//              output start of every (bucket, tile) run; offsets[b] is the
-//              value at (b, 0).
+//  1. hist:    one LDS histogram per tile of rows -> hist[t * P + b]
+//              (tile-major: a tile's counts are one contiguous row)
+//  2. offsets: column-wise scan turning counts into the output start of every
+//              (tile, bucket) run, plus the bucket starts offsets[0..P].
 //  3. scatter: per tile, each wave ranks its rows inside their bucket with
 //              ballots (stable: rows keep input order), the block turns ranks
 //              into tile-local positions, and every column is staged in LDS in
 //              bucket order and written out as contiguous runs.  Tiles are
 //              mapped so that each XCD works on one contiguous range of tiles,
 //              keeping the partial lines at run boundaries in one L2.
+#include <cstdlib>
+
 #include "gq_device.h"
 #include "gq_internal.h"
 #include "gq_ops.h"
@@ -28,25 +30,29 @@ struct part_cols {
     int32_t n;
 };
 
+// Bucket = LOG2P bits of fmix64(key) starting at bit `shift` (the public
+// operator uses the top bits: shift = 64 - LOG2P).
 template <int LOG2P>
-GQ_DEV uint32_t bucket_of(int64_t key)
+GQ_DEV uint32_t bucket_of(int64_t key, int shift)
 {
     if constexpr (LOG2P == 0) {
         (void)key;
+        (void)shift;
         return 0;
     } else {
-        return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(key)) >> (64 - LOG2P));
+        return static_cast<uint32_t>((gq_fmix64(static_cast<uint64_t>(key)) >> shift) & ((1u << LOG2P) - 1));
     }
 }
 
+// LDS histogram of one tile, written as the tile's row hist[t * P + b].
 template <int LOG2P, int ITEMS>
 __global__ __launch_bounds__(PT_THREADS) void part_hist_kernel(const int64_t *__restrict__ key, int64_t n,
-                                                               uint32_t *__restrict__ hist, int64_t ntiles)
+                                                               int shift, uint32_t *__restrict__ hist)
 {
     constexpr int P = 1 << LOG2P;
     constexpr int TILE = PT_THREADS * ITEMS;
     __shared__ uint32_t h[P];
-    for (int b = threadIdx.x; b < P; b += PT_THREADS) h[b] = 0;
+    for (int i = threadIdx.x; i < P; i += PT_THREADS) h[i] = 0;
     __syncthreads();
     const int64_t base = static_cast<int64_t>(blockIdx.x) * TILE;
     int64_t k[ITEMS];
@@ -58,22 +64,21 @@ __global__ __launch_bounds__(PT_THREADS) void part_hist_kernel(const int64_t *__
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         const int64_t e = base + c * PT_THREADS + threadIdx.x;
-        if (e < n) atomicAdd(&h[bucket_of<LOG2P>(k[c])], 1u);
+        if (e < n) atomicAdd(&h[bucket_of<LOG2P>(k[c], shift)], 1u);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < P; b += PT_THREADS) hist[static_cast<int64_t>(b) * ntiles + blockIdx.x] = h[b];
+    for (int b = threadIdx.x; b < P; b += PT_THREADS) hist[static_cast<int64_t>(blockIdx.x) * P + b] = h[b];
 }
 
-__global__ void part_offsets_kernel(const uint32_t *__restrict__ scanned, int64_t ntiles, int P, int64_t n,
-                                    int64_t *__restrict__ offsets)
+__global__ void part_offsets_kernel(const uint32_t *__restrict__ start, int P, int64_t *__restrict__ offsets)
 {
-    for (int b = threadIdx.x; b <= P; b += blockDim.x)
-        offsets[b] = (b < P) ? static_cast<int64_t>(scanned[static_cast<int64_t>(b) * ntiles]) : n;
+    for (int b = threadIdx.x; b <= P; b += blockDim.x) offsets[b] = static_cast<int64_t>(start[b]);
 }
 
 template <int LOG2P, int ITEMS>
 __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t *__restrict__ key, int64_t n,
-                                                                  const uint32_t *__restrict__ gofs, int64_t ntiles,
+                                                                  int shift, const uint32_t *__restrict__ gofs,
+                                                                  int64_t ntiles,
                                                                   int64_t *__restrict__ key_out,
                                                                   int32_t *__restrict__ rowid_out, part_cols cols)
 {
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         const bool valid = row0 + c * 64 < n;
-        const uint32_t b = bucket_of<LOG2P>(k[c]);
+        const uint32_t b = bucket_of<LOG2P>(k[c], shift);
         uint64_t match = gq_ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < LOG2P; ++bit) {
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
     const uint32_t excl = gq_block_exclusive_scan<PT_THREADS>(threadIdx.x < P ? tot : 0u, &all, scan_smem);
     if (threadIdx.x < P) {
         lstart[threadIdx.x] = excl;
-        gstart[threadIdx.x] = gofs[static_cast<int64_t>(threadIdx.x) * ntiles + tile];
+        gstart[threadIdx.x] = gofs[static_cast<int64_t>(tile) * P + threadIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -195,42 +200,111 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
     }
 }
 
-constexpr int PT_ITEMS = 16;
-constexpr int PT_TILE = PT_THREADS * PT_ITEMS;
+// Rows per thread in the scatter (tile = 256 * items).  16 by default; the
+// GQ_PARTITION_ITEMS environment variable (8, 16 or 32) overrides it.
+int part_items()
+{
+    static int v = [] {
+        const char *e = getenv("GQ_PARTITION_ITEMS");
+        const int x = e ? atoi(e) : 16;
+        return (x == 8 || x == 16 || x == 32) ? x : 16;
+    }();
+    return v;
+}
+
+constexpr int PT_MIN_TILE = PT_THREADS * 8;
 
 struct part_ws {
     uint32_t *hist;
+    uint32_t *start;
     void *scan_ws;
 };
 
+// The workspace is sized for the smallest tile, so it fits every choice.
 part_ws part_layout(gq_carver &c, int64_t n, int log2p)
 {
     part_ws w;
-    const int64_t ntiles = n > 0 ? (n + PT_TILE - 1) / PT_TILE : 1;
+    const int64_t ntiles = n > 0 ? (n + PT_MIN_TILE - 1) / PT_MIN_TILE : 1;
     const int64_t cells = ntiles << log2p;
     w.hist = c.take<uint32_t>(static_cast<size_t>(cells));
-    w.scan_ws = c.take<char>(gq_scan_u32_workspace(cells));
+    w.start = c.take<uint32_t>((size_t(1) << log2p) + 1);
+    w.scan_ws = c.take<char>(gq_tile_offsets_workspace(ntiles, 1 << log2p));
     return w;
 }
 
-template <int LOG2P>
-gq_status run_partition(gq_ctx *ctx, const int64_t *key, int64_t n, const part_cols &cols, int64_t *key_out,
-                        int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s)
+template <int LOG2P, int ITEMS>
+gq_status run_partition_items(gq_ctx *ctx, const int64_t *key, int64_t n, int shift, const part_cols &cols,
+                              int64_t *key_out, int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s,
+                              const gq_part_names &nm)
 {
     constexpr int P = 1 << LOG2P;
-    const int64_t ntiles = n > 0 ? (n + PT_TILE - 1) / PT_TILE : 1;
+    constexpr int TILE = PT_THREADS * ITEMS;
+    const int64_t ntiles = n > 0 ? (n + TILE - 1) / TILE : 1;
     const uint32_t grid = static_cast<uint32_t>(ntiles);
-    GQ_TRY(gq_launch(ctx, "gq_partition_hist", part_hist_kernel<LOG2P, PT_ITEMS>, dim3(grid), dim3(PT_THREADS), 0,
-                     s, key, n, w.hist, ntiles));
-    GQ_TRY(gq_scan_u32(ctx, w.hist, ntiles * P, w.scan_ws, s));
-    GQ_TRY(gq_launch(ctx, "gq_partition_offsets", part_offsets_kernel, dim3(1), dim3(256), 0, s,
-                     static_cast<const uint32_t *>(w.hist), ntiles, P, n, offsets));
+    GQ_TRY(gq_launch(ctx, nm.hist, part_hist_kernel<LOG2P, ITEMS>, dim3(grid), dim3(PT_THREADS), 0, s, key, n,
+                     shift, w.hist));
+    GQ_TRY(gq_tile_offsets(ctx, w.hist, ntiles, P, w.start, w.scan_ws, s, nm.scan));
+    GQ_TRY(gq_launch(ctx, nm.offsets, part_offsets_kernel, dim3(1), dim3(256), 0, s,
+                     static_cast<const uint32_t *>(w.start), P, offsets));
     if (n == 0) return GQ_OK;
-    return gq_launch(ctx, "gq_partition_scatter", part_scatter_kernel<LOG2P, PT_ITEMS>, dim3(grid), dim3(PT_THREADS),
-                     0, s, key, n, static_cast<const uint32_t *>(w.hist), ntiles, key_out, rowid_out, cols);
+    return gq_launch(ctx, nm.scatter, part_scatter_kernel<LOG2P, ITEMS>, dim3(grid), dim3(PT_THREADS),
+                     0, s, key, n, shift, static_cast<const uint32_t *>(w.hist), ntiles, key_out, rowid_out,
+                     cols);
+}
+
+template <int LOG2P>
+gq_status run_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int shift, const part_cols &cols,
+                        int64_t *key_out, int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s,
+                        const gq_part_names &nm)
+{
+    switch (part_items()) {
+    case 8: return run_partition_items<LOG2P, 8>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
+    case 32: return run_partition_items<LOG2P, 32>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
+    default: return run_partition_items<LOG2P, 16>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
+    }
+}
+
+gq_status dispatch_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, const part_cols &pc,
+                             int64_t *key_out, int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s,
+                             const gq_part_names &nm)
+{
+    switch (log2p) {
+    case 0: return run_partition<0>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 1: return run_partition<1>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 2: return run_partition<2>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 3: return run_partition<3>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 4: return run_partition<4>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 5: return run_partition<5>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 6: return run_partition<6>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 7: return run_partition<7>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    default: return run_partition<8>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    }
 }
 
 }  // namespace
+
+size_t gq_partition_bits_workspace(int64_t n, int log2p)
+{
+    gq_carver c(nullptr);
+    part_layout(c, n < 0 ? 0 : n, log2p);
+    return c.bytes();
+}
+
+gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, int ncols,
+                            void *const *cols, const int32_t *col_bytes, int64_t *key_out, void *const *cols_out,
+                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &nm)
+{
+    part_cols pc{};
+    pc.n = ncols;
+    for (int i = 0; i < ncols; ++i) {
+        pc.in[i] = cols[i];
+        pc.out[i] = cols_out[i];
+        pc.bytes[i] = col_bytes[i];
+    }
+    gq_carver c(ws);
+    part_ws w = part_layout(c, n, log2p);
+    return dispatch_partition(ctx, key, n, log2p, shift, pc, key_out, nullptr, offsets, w, s, nm);
+}
 
 extern "C" {
 
@@ -274,17 +348,10 @@ gq_status gq_radix_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log
     hipStream_t s = static_cast<hipStream_t>(stream);
     gq_carver c(ws);
     part_ws w = part_layout(c, n, log2_fanout);
-    switch (log2_fanout) {
-    case 0: return run_partition<0>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 1: return run_partition<1>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 2: return run_partition<2>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 3: return run_partition<3>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 4: return run_partition<4>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 5: return run_partition<5>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 6: return run_partition<6>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    case 7: return run_partition<7>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    default: return run_partition<8>(ctx, key, n, pc, key_out, rowid_out, offsets_dev, w, s);
-    }
+    static const gq_part_names names{"gq_partition_hist", "gq_partition_scan", "gq_partition_offsets",
+                                     "gq_partition_scatter"};
+    return dispatch_partition(ctx, key, n, log2_fanout, 64 - log2_fanout, pc, key_out, rowid_out, offsets_dev, w, s,
+                              names);
 }
 
 }  // extern "C"

@@ -54,7 +54,7 @@ size_t gq_scan_u32_workspace(int64_t n)
     return c.bytes();
 }
 
-gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStream_t s)
+gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStream_t s, const char *name)
 {
     if (n <= 0) return GQ_OK;
     gq_carver c(ws);
@@ -62,6 +62,112 @@ gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStrea
     uint32_t *ctr = c.take<uint32_t>(64);
     uint64_t *status = c.take<uint64_t>(static_cast<size_t>(tiles));
     GQ_TRY(gq_zero(ctx, ws, c.off / 4, s));
-    return gq_launch(ctx, "gq_scan", scan_u32_kernel, dim3(static_cast<uint32_t>(tiles)), dim3(SC_THREADS), 0, s,
+    return gq_launch(ctx, name, scan_u32_kernel, dim3(static_cast<uint32_t>(tiles)), dim3(SC_THREADS), 0, s,
                      data, n, ctr, status);
+}
+
+// ---------------------------------------------------------------------------
+// Run offsets from per-tile bucket counts in TILE-MAJOR layout (the counts of
+// one tile are contiguous, so a histogram kernel writes them, and a scatter
+// kernel reads its tile's P offsets, as one coalesced row):
+//
+//   off[t*P + b] = start[b] + sum_{t' < t} cnt[t'*P + b],
+//   start[b]     = sum_{b' < b} total[b'],   start[P] = sum of all counts.
+//
+// Four small kernels, every access coalesced across buckets: per-chunk column
+// sums (a chunk = TO_CHUNK tiles), a scan of those sums down each column, an
+// exclusive scan of the bucket totals, and the final per-tile offsets.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int TO_CHUNK = 256;
+constexpr int TO_THREADS = 256;
+constexpr int TO_MAX_P = 1024;
+
+__global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
+                                                                  int P, uint32_t *__restrict__ csum)
+{
+    const int64_t c = blockIdx.x;
+    const int b = blockIdx.y * TO_THREADS + threadIdx.x;
+    if (b >= P) return;
+    const int64_t t0 = c * TO_CHUNK;
+    const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (int64_t t = t0; t < t1; ++t) s += cnt[t * P + b];
+    csum[c * P + b] = s;
+}
+
+__global__ __launch_bounds__(TO_THREADS) void to_chunk_scan_kernel(uint32_t *__restrict__ csum, int64_t nchunks,
+                                                                   int P, uint32_t *__restrict__ total)
+{
+    const int b = blockIdx.x * TO_THREADS + threadIdx.x;
+    if (b >= P) return;
+    uint32_t run = 0;
+#pragma unroll 8
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const uint32_t x = csum[c * P + b];
+        csum[c * P + b] = run;
+        run += x;
+    }
+    total[b] = run;
+}
+
+__global__ __launch_bounds__(TO_MAX_P) void to_bucket_start_kernel(const uint32_t *__restrict__ total, int P,
+                                                                   uint32_t *__restrict__ start)
+{
+    __shared__ uint32_t smem[TO_MAX_P / 64];
+    const uint32_t v = threadIdx.x < static_cast<unsigned>(P) ? total[threadIdx.x] : 0u;
+    uint32_t all;
+    const uint32_t ex = gq_block_exclusive_scan<TO_MAX_P>(v, &all, smem);
+    if (threadIdx.x < static_cast<unsigned>(P)) start[threadIdx.x] = ex;
+    if (threadIdx.x == 0) start[P] = all;
+}
+
+__global__ __launch_bounds__(TO_THREADS) void to_final_kernel(uint32_t *__restrict__ cnt, int64_t ntiles, int P,
+                                                              const uint32_t *__restrict__ csum,
+                                                              const uint32_t *__restrict__ start)
+{
+    const int64_t c = blockIdx.x;
+    const int b = blockIdx.y * TO_THREADS + threadIdx.x;
+    if (b >= P) return;
+    const int64_t t0 = c * TO_CHUNK;
+    const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
+    uint32_t run = start[b] + csum[c * P + b];
+#pragma unroll 8
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint32_t x = cnt[t * P + b];
+        cnt[t * P + b] = run;
+        run += x;
+    }
+}
+
+}  // namespace
+
+size_t gq_tile_offsets_workspace(int64_t ntiles, int P)
+{
+    gq_carver c(nullptr);
+    const int64_t nchunks = (ntiles + TO_CHUNK - 1) / TO_CHUNK;
+    c.take<uint32_t>(static_cast<size_t>((nchunks > 0 ? nchunks : 1) * P));
+    c.take<uint32_t>(static_cast<size_t>(P));
+    return c.bytes();
+}
+
+gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
+                          hipStream_t s, const char *name)
+{
+    if (P < 1 || P > TO_MAX_P || ntiles < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_tile_offsets: bad shape");
+    gq_carver c(ws);
+    const int64_t nchunks = (ntiles + TO_CHUNK - 1) / TO_CHUNK;
+    uint32_t *csum = c.take<uint32_t>(static_cast<size_t>(nchunks * P));
+    uint32_t *total = c.take<uint32_t>(static_cast<size_t>(P));
+    const dim3 grid2(static_cast<uint32_t>(nchunks), static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
+    const dim3 grid1(static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
+    GQ_TRY(gq_launch(ctx, name, to_chunk_sum_kernel, grid2, dim3(TO_THREADS), 0, s,
+                     static_cast<const uint32_t *>(cnt), ntiles, P, csum));
+    GQ_TRY(gq_launch(ctx, name, to_chunk_scan_kernel, grid1, dim3(TO_THREADS), 0, s, csum, nchunks, P, total));
+    GQ_TRY(gq_launch(ctx, name, to_bucket_start_kernel, dim3(1), dim3(TO_MAX_P), 0, s,
+                     static_cast<const uint32_t *>(total), P, start));
+    return gq_launch(ctx, name, to_final_kernel, grid2, dim3(TO_THREADS), 0, s, cnt, ntiles, P,
+                     static_cast<const uint32_t *>(csum), static_cast<const uint32_t *>(start));
 }

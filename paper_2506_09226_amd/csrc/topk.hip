@@ -128,22 +128,34 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
+    // software pipeline: the next step's rows are loaded before this step's
+    // candidates are offered, so the loads overlap the LDS work and barriers
+    int64_t v[TK_STEP_ITEMS], vn[TK_STEP_ITEMS];
+    int32_t r[TK_STEP_ITEMS], rn[TK_STEP_ITEMS];
+#pragma unroll
+    for (int c = 0; c < TK_STEP_ITEMS; ++c) {
+        const int64_t j = j0 + c * TK_THREADS + threadIdx.x;
+        r[c] = 0;
+        v[c] = 0;
+        if (j < j1) {
+            r[c] = sel ? sel[j] : static_cast<int32_t>(j);
+            v[c] = val[r[c]];
+        }
+    }
     for (int64_t s = j0; s < j1; s += TK_STEP) {
+#pragma unroll
+        for (int c = 0; c < TK_STEP_ITEMS; ++c) {
+            const int64_t j = s + TK_STEP + c * TK_THREADS + threadIdx.x;
+            rn[c] = 0;
+            vn[c] = 0;
+            if (j < j1) {
+                rn[c] = sel ? sel[j] : static_cast<int32_t>(j);
+                vn[c] = val[rn[c]];
+            }
+        }
         const uint64_t th_ok = L.th_ok;
         const uint32_t th_rk = L.th_rk;
         const bool has_th = L.has_th != 0;
-        int64_t v[TK_STEP_ITEMS];
-        int32_t r[TK_STEP_ITEMS];
-#pragma unroll
-        for (int c = 0; c < TK_STEP_ITEMS; ++c) {
-            const int64_t j = s + c * TK_THREADS + threadIdx.x;
-            r[c] = 0;
-            v[c] = 0;
-            if (j < j1) {
-                r[c] = sel ? sel[j] : static_cast<int32_t>(j);
-                v[c] = val[r[c]];
-            }
-        }
 #pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
             const int64_t j = s + c * TK_THREADS + threadIdx.x;
@@ -154,6 +166,11 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
         const uint32_t cnt_now = L.count;      // same value in every thread
         __syncthreads();
         if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_compact(L, k);
+#pragma unroll
+        for (int c = 0; c < TK_STEP_ITEMS; ++c) {
+            v[c] = vn[c];
+            r[c] = rn[c];
+        }
     }
     tk_compact(L, k);
     const uint32_t cnt = L.count < static_cast<uint32_t>(k) ? L.count : static_cast<uint32_t>(k);
@@ -228,7 +245,7 @@ tk_ws tk_layout(gq_carver &c, int64_t n, int k, int num_cus)
 {
     tk_ws w;
     int64_t blocks = (n + 4 * TK_STEP - 1) / (4 * TK_STEP);     // at least 4 steps per block
-    const int64_t maxb = static_cast<int64_t>(num_cus) * 2;
+    const int64_t maxb = static_cast<int64_t>(num_cus) * 3;
     if (blocks > maxb) blocks = maxb;
     if (blocks < 1) blocks = 1;
     int64_t chunk = (n + blocks - 1) / blocks;

@@ -37,6 +37,7 @@ class PlainPipeline:
         self.n_sel = torch.zeros(1, dtype=torch.int64, device=d)
         self.ws_filter = ctx.workspace(L.gq_filter_workspace_bytes(n))
         self.table = torch.empty(gq_join_table_bytes(m, load_factor), dtype=torch.uint8, device=d)
+        self.ws_build = ctx.workspace(L.gq_join_build_workspace_bytes(m, self.table.numel()))
         self.prow = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.pay = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
@@ -64,7 +65,7 @@ class PlainPipeline:
                                outs=(self.p_key, self.p_cols, self.p_rowid, self.p_off), ws=self.ws_part)
         fk, date, qty, price, disc = self.columns()
         gq_filter(ctx, date, -(1 << 31), self.date_hi, out=self.sel, n_out=self.n_sel, ws=self.ws_filter)
-        gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table)
+        gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table, ws=self.ws_build)
         gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
                       payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
         gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,

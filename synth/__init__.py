@@ -255,3 +255,59 @@ def workload(idx: int, scale: float = 1.0) -> Workload:
                         FactSpec(int(n * scale), mm, seed, zipf_s=1.0, g32_range=2), mm, seed,
                         25, 128)
     raise ValueError(idx)
+
+
+# ----------------------------------------------------------------------------
+# Batched workload: many independent small join + aggregate instances
+# ----------------------------------------------------------------------------
+
+@dataclass
+class BatchSpec:
+    count: int = 512
+    build_lo: float = 1e3
+    build_hi: float = 2e6
+    ratio_lo: float = 8.0
+    ratio_hi: float = 16.0
+    seed: int = SEED_BASE + 3
+    attr_range: int = 25
+    date_hi: int = 1500
+
+
+def batch_sizes(spec: BatchSpec, scale: float = 1.0):
+    """(m_i, n_i) per instance: m log-uniform in [build_lo, build_hi], n = round(m * U[ratio])."""
+    ms = log_uniform_sizes(spec.count, spec.build_lo, spec.build_hi, spec.seed)
+    rs = uniform_reals(spec.count, spec.ratio_lo, spec.ratio_hi, spec.seed, 98)
+    out = []
+    for m, r in zip(ms, rs):
+        mm = max(1, int(m * scale))
+        out.append((mm, int(round(mm * r))))
+    return out
+
+
+def batch_tables(spec: BatchSpec, device="cpu", scale: float = 1.0):
+    """Dimension and fact columns of every instance, stored back to back in one
+    tensor per column; returns (columns, [(dim_offset, m, fact_offset, n)])."""
+    sizes = batch_sizes(spec, scale)
+    M = sum(m for m, _ in sizes)
+    N = sum(n for _, n in sizes)
+    cols = {"dim_key": torch.empty(M, dtype=torch.int64, device=device),
+            "dim_attr": torch.empty(M, dtype=torch.int32, device=device),
+            "fk": torch.empty(N, dtype=torch.int64, device=device),
+            "date": torch.empty(N, dtype=torch.int32, device=device),
+            "qty": torch.empty(N, dtype=torch.int64, device=device),
+            "price": torch.empty(N, dtype=torch.int64, device=device),
+            "disc": torch.empty(N, dtype=torch.int64, device=device)}
+    layout = []
+    mo = no = 0
+    for i, (m, n) in enumerate(sizes):
+        seed = spec.seed + 1 + i
+        d = dim_table(m, seed, spec.attr_range, device=device)
+        cols["dim_key"][mo:mo + m] = d["key"]
+        cols["dim_attr"][mo:mo + m] = d["attr"]
+        f = fact_table(FactSpec(n, m, seed), device=device)
+        for k in ("fk", "date", "qty", "price", "disc"):
+            cols[k][no:no + n] = f[k]
+        layout.append((mo, m, no, n))
+        mo += m
+        no += n
+    return cols, layout

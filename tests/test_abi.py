@@ -21,7 +21,7 @@ def _declared():
 def test_library_exports_every_declared_symbol():
     L = gq.lib()
     names = _declared()
-    assert len(names) >= 19
+    assert len(names) >= 20
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
     assert sorted(gq.EXPORTED) == names
@@ -47,12 +47,15 @@ def test_workspace_queries_monotone():
     large = L.gq_groupby_workspace_bytes(1 << 20, 1_500_000, 0, 1)
     assert 0 < small < large
     assert L.gq_topk_workspace_bytes(1 << 20, 100) > 0
+    small = L.gq_join_build_workspace_bytes(1000, gq.gq_join_table_bytes(1000, 0.5))
+    big = L.gq_join_build_workspace_bytes(25_000_000, gq.gq_join_table_bytes(25_000_000, 0.5))
+    assert small == 256 and big > 25_000_000 * 24
 
 
 def test_null_context_rejected():
     L = gq.lib()
     assert L.gq_filter(None, None, 4, 10, None, None, 0, 1, None, None, None, 0, None) == gq.GQ_ERR_INVALID_ARG
-    assert L.gq_join_build(None, None, None, 0, None, None, None, 0, None) == gq.GQ_ERR_INVALID_ARG
+    assert L.gq_join_build(None, None, None, 0, None, None, None, 0, None, 0, None) == gq.GQ_ERR_INVALID_ARG
     assert L.gq_topk(None, None, None, 0, None, 1, 1, None, None, None, None, 0, None) == gq.GQ_ERR_INVALID_ARG
     assert L.gq_status_word(None, None, None) == gq.GQ_ERR_INVALID_ARG
     assert L.gq_last_error(None) == b""

@@ -1,0 +1,125 @@
+"""The batched persistent form: every instance equals the oracle, the plain
+per-instance form, and itself under every candidate tuning."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2506_09226_amd as gq
+from paper_2506_09226_amd.batch import BatchedJoinAgg, PlainPerInstance
+
+pytestmark = pytest.mark.gpu
+AVG_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = gq.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    spec = synth.BatchSpec(count=48)
+    cols, layout = synth.batch_tables(spec, device="cuda", scale=0.004)   # m in ~[4, 8000]
+    return spec, cols, layout
+
+
+def _sorted(h):
+    o = np.argsort(h["key32"], kind="stable")
+    return {k: (None if v is None else v[o]) for k, v in h.items()}
+
+
+def _equal(a, b):
+    for f in ("key32", "count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
+        assert np.array_equal(a[f], b[f]), f
+    for f in ("avg_qty", "avg_rev"):
+        np.testing.assert_allclose(a[f], b[f], rtol=AVG_RTOL, atol=0)
+
+
+def _oracle(cols_h, lay, spec):
+    mo, m, no, n = lay
+    date = cols_h["date"][no:no + n]
+    sel = oracle.filter(date, 0, spec.date_hi)
+    prow, pay = oracle.join(cols_h["dim_key"][mo:mo + m], cols_h["dim_attr"][mo:mo + m], cols_h["fk"][no:no + n], sel)
+    return oracle.groupby(len(prow), cols_h["qty"][no:no + n], cols_h["price"][no:no + n],
+                          cols_h["disc"][no:no + n], rowid=prow, key32=pay)
+
+
+def test_batch_equals_oracle_and_plain(ctx, small_batch):
+    spec, cols, layout = small_batch
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    assert ctx.status() == gq.GQ_OK
+    p = PlainPerInstance(ctx, cols, layout, 0, spec.date_hi)
+    p.run()
+    assert ctx.status() == gq.GQ_OK
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    for lay, gb, gp in zip(layout, b.results(), p.results()):
+        e = _oracle(cols_h, lay, spec)
+        _equal(_sorted(gb), e)
+        _equal(_sorted(gp), e)
+
+
+@pytest.mark.parametrize("lf,tile,lag,build", [(0.5, 4096, 0, 256), (0.7, 16384, 3, 1024), (0.9, 8192, 1, 4096),
+                                               (0.3, 65536, 47, 256)])
+def test_batch_tunings_identical(ctx, small_batch, lf, tile, lag, build):
+    spec, cols, layout = small_batch
+    ref = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    ref.run()
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    t = gq.gq_default_tuning()
+    t.load_factor, t.probe_tile, t.lag, t.build_tile, t.init_tile = lf, tile, lag, build, 1024
+    b.tuning = t
+    b.run()
+    assert ctx.status() == gq.GQ_OK
+    for ga, gb in zip(ref.results(), b.results()):
+        _equal(_sorted(ga), _sorted(gb))
+
+
+def test_batch_large_instances_use_device_builds(ctx):
+    """Instances big enough for the init/build work items (tables > 4096 slots),
+    mixed with tiny ones and an empty fact side."""
+    spec = synth.BatchSpec(count=6, build_lo=3000, build_hi=200_000, seed=synth.SEED_BASE + 77)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    layout = list(layout)
+    mo, m, no, n = layout[0]
+    layout[0] = (mo, m, no, 0)                     # no fact rows: zero groups
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    assert ctx.status() == gq.GQ_OK
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    res = b.results()
+    assert len(res[0]["count"]) == 0
+    for lay, g in zip(layout[1:], res[1:]):
+        _equal(_sorted(g), _oracle(cols_h, lay, spec))
+
+
+def test_batch_autotune_and_cache(ctx, small_batch, tmp_path):
+    spec, cols, layout = small_batch
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    path = str(tmp_path / "tune.txt")
+    t1, ms1 = b.autotune(path)
+    assert ms1 > 0 and t1.probe_tile % 4096 == 0
+    b2 = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    t2, ms2 = b2.autotune(path)                     # served from the cache
+    assert t2.as_dict() == t1.as_dict() and ms2 == pytest.approx(ms1, rel=1e-3)
+    b2.run()
+    ref = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    ref.run()
+    for ga, gb in zip(ref.results(), b2.results()):
+        _equal(_sorted(ga), _sorted(gb))
+
+
+def test_batch_duplicate_key_reported(ctx):
+    spec = synth.BatchSpec(count=3, build_lo=100, build_hi=10_000, seed=synth.SEED_BASE + 91)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    mo, m, _, _ = layout[1]
+    cols["dim_key"][mo + 1] = cols["dim_key"][mo]
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY

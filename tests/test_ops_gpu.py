@@ -157,6 +157,43 @@ def test_join_high_load_factor_and_device_counts(ctx):
     assert k == len(ep) and np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
 
 
+@pytest.fixture
+def build_path(request, monkeypatch):
+    monkeypatch.setenv("GQ_JOIN_BUILD", request.param)
+    return request.param
+
+
+@pytest.mark.parametrize("build_path", ["cas", "region"], indirect=True)
+@pytest.mark.parametrize("m,lf", [(300_000, 0.5), (1_200_000, 0.5), (900_000, 0.9), (70_000, 0.9)])
+def test_join_build_paths(ctx, build_path, m, lf):
+    """Both builds (device CAS; LDS regions after a radix partition, including
+    the two-pass case and region overflow at load factor 0.9) give tables on
+    which the probe equals the oracle."""
+    r = rng(m)
+    bkey, bpay = _dim(m, m + 1)
+    n = 400_000
+    fk = np.where(r.random(n) < 0.9, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
+    fk = fk.astype(np.int64)
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), load_factor=lf)
+    assert ctx.status() == gq.GQ_OK
+    ep, ey = oracle.join(bkey, bpay, fk)
+    prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(fk))
+    k = int(cnt.item())
+    assert k == len(ep) and np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
+
+
+@pytest.mark.parametrize("build_path", ["region"], indirect=True)
+def test_join_region_build_errors(ctx, build_path):
+    keys = np.arange(300_000, dtype=np.int64) * 7 + 1
+    keys[123_456] = keys[77]
+    gq.gq_join_build(ctx, dev(keys), dev(np.zeros(300_000, np.int32)))
+    assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
+    keys = np.arange(300_000, dtype=np.int64) * 7 + 1
+    keys[5] = -(1 << 63)
+    gq.gq_join_build(ctx, dev(keys), dev(np.zeros(300_000, np.int32)))
+    assert ctx.status() == gq.GQ_ERR_INVALID_KEY
+
+
 def test_join_duplicate_and_invalid_keys(ctx):
     gq.gq_join_build(ctx, dev(np.array([5, 6, 5], np.int64)), dev(np.zeros(3, np.int32)))
     assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
