@@ -224,6 +224,9 @@ typedef struct gq_groupby_in {
     const int64_t *price;      /* device int64, read at v                   */
     const int64_t *disc;       /* device int64, read at v                   */
     int64_t rev_scale;         /* e.g. 100 (percent)                        */
+    const int32_t *filter;     /* nullable device int32 read at v: only rows */
+    int64_t filter_lo;         /*   with filter_lo <= filter[v] < filter_hi  */
+    int64_t filter_hi;         /*   are aggregated                           */
 } gq_groupby_in;
 
 /* Output groups, one entry per distinct key present, in unspecified order.
@@ -335,6 +338,76 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
 size_t gq_batch_autotune_workspace_bytes(const gq_instance *inst, int n_inst);
 gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, const char *cache_path,
                             gq_tuning *best, double *best_ms, void *ws, size_t ws_bytes, gq_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Served queries: a request loop over tables resident in HBM.
+ * The paper's queries are interactive and recurring over data kept resident
+ * in HBM (Sec. 4.2); the server admits queries by their memory footprint,
+ * batches queries of one template that arrive while others run, and runs a
+ * batch as one shared scan of the fact columns, with batches of different
+ * templates overlapping on separate HIP streams (continuous batching).
+ * ------------------------------------------------------------------------ */
+
+#define GQ_QUERY_FILTER_AGG   1   /* date < date_hi, group by disc (key64)          */
+#define GQ_QUERY_JOIN_AGG     2   /* + join fk = dim1 key, group by dim1 attr (key32) */
+#define GQ_QUERY_JOIN2_AGG    3   /* + join fk = dim1, fk2 = dim2, group by dim2 attr */
+#define GQ_QUERY_FILTER_TOPK  4   /* date < date_hi, top-k price (desc, ties by row) */
+
+typedef struct gq_server_tables {
+    const int64_t *fk, *fk2;   /* device fact columns, n rows each          */
+    const int32_t *date;
+    const int64_t *qty, *price, *disc;
+    int64_t n;
+    const void *dim1_table;    /* join tables from gq_join_build; payload = */
+    size_t dim1_table_bytes;   /*   the dimension attribute                 */
+    const void *dim2_table;
+    size_t dim2_table_bytes;
+} gq_server_tables;
+
+typedef struct gq_server_cfg {
+    gq_server_tables tables;   /* resident; must outlive the server         */
+    void *pool;                /* device memory for query workspaces        */
+    size_t pool_bytes;         /*   (caller-owned, 256-byte aligned)        */
+    int32_t streams;           /* batches in flight at once, 1..8           */
+    int32_t max_batch;         /* queries per shared-scan batch, 1..16      */
+    int32_t serial;            /* 1: each query alone with the plain
+                                  operators, one at a time, arrival order   */
+} gq_server_cfg;
+
+typedef struct gq_query {
+    int32_t kind;              /* GQ_QUERY_*                                 */
+    int32_t k;                 /* top-k size (FILTER_TOPK, 1..256)          */
+    int64_t date_hi;           /* keep fact rows with date < date_hi        */
+    int64_t max_groups;        /* aggregate templates: groups bound         */
+    gq_groups groups;          /* aggregate outputs (device, caller-owned)  */
+    int64_t *topk_val;         /* FILTER_TOPK outputs (device, k entries)   */
+    int32_t *topk_row;
+    int64_t *topk_n;
+} gq_query;
+
+typedef struct gq_server gq_server;
+
+/* Start a server on `device` (it creates its own context and a scheduler
+ * thread).  Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
+gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out);
+
+/* Queue a query; *ticket identifies it.  The query's output buffers must stay
+ * valid until gq_server_wait returns for the ticket.  Thread-safe.
+ * Errors: GQ_ERR_INVALID_ARG (bad query), GQ_ERR_CAPACITY (its workspace can
+ * never fit the pool), GQ_ERR_UNSUPPORTED (max_groups > 512 for FILTER_AGG or
+ * JOIN2_AGG in batched mode, k > 256). */
+gq_status gq_server_submit(gq_server *srv, const gq_query *q, uint64_t *ticket);
+
+/* Block until the query has finished on the device; *latency_s = seconds from
+ * submit to completion; *query_status = GQ_OK or a launch error.  Each
+ * ticket can be waited for once.  Thread-safe. */
+gq_status gq_server_wait(gq_server *srv, uint64_t ticket, gq_status *query_status, double *latency_s);
+
+/* Counters: queries finished, batches launched, largest batch. */
+gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen);
+
+/* Finish every queued query, stop the scheduler, release the context. */
+void gq_server_destroy(gq_server *srv);
 
 #ifdef __cplusplus
 }

@@ -37,8 +37,11 @@ EXPORTED = [
     "gq_radix_partition", "gq_join_table_bytes", "gq_join_build_workspace_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
     "gq_join_probe", "gq_groupby_workspace_bytes", "gq_groupby_agg", "gq_topk_workspace_bytes", "gq_topk",
     "gq_default_tuning", "gq_batch_workspace_bytes", "gq_batch_join_agg", "gq_batch_autotune_workspace_bytes",
-    "gq_batch_autotune",
+    "gq_batch_autotune", "gq_server_create", "gq_server_submit", "gq_server_wait", "gq_server_stats",
+    "gq_server_destroy",
 ]
+
+GQ_QUERY_FILTER_AGG, GQ_QUERY_JOIN_AGG, GQ_QUERY_JOIN2_AGG, GQ_QUERY_FILTER_TOPK = 1, 2, 3, 4
 
 
 class GQError(RuntimeError):
@@ -51,7 +54,8 @@ class GroupbyIn(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_dev", C.c_void_p), ("rowid", C.c_void_p),
                 ("key64", C.c_void_p), ("key64_by_rowid", C.c_int32),
                 ("key32", C.c_void_p), ("key32_by_rowid", C.c_int32),
-                ("qty", C.c_void_p), ("price", C.c_void_p), ("disc", C.c_void_p), ("rev_scale", C.c_int64)]
+                ("qty", C.c_void_p), ("price", C.c_void_p), ("disc", C.c_void_p), ("rev_scale", C.c_int64),
+                ("filter", C.c_void_p), ("filter_lo", C.c_int64), ("filter_hi", C.c_int64)]
 
 
 class Groups(C.Structure):
@@ -65,6 +69,22 @@ class Instance(C.Structure):
                 ("fk", C.c_void_p), ("date", C.c_void_p), ("qty", C.c_void_p), ("price", C.c_void_p),
                 ("disc", C.c_void_p), ("n", C.c_int64), ("date_lo", C.c_int64), ("date_hi", C.c_int64),
                 ("rev_scale", C.c_int64), ("out", Groups)]
+
+
+class ServerTables(C.Structure):
+    _fields_ = [("fk", C.c_void_p), ("fk2", C.c_void_p), ("date", C.c_void_p), ("qty", C.c_void_p),
+                ("price", C.c_void_p), ("disc", C.c_void_p), ("n", C.c_int64), ("dim1_table", C.c_void_p),
+                ("dim1_table_bytes", C.c_size_t), ("dim2_table", C.c_void_p), ("dim2_table_bytes", C.c_size_t)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("tables", ServerTables), ("pool", C.c_void_p), ("pool_bytes", C.c_size_t),
+                ("streams", C.c_int32), ("max_batch", C.c_int32), ("serial", C.c_int32)]
+
+
+class Query(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("k", C.c_int32), ("date_hi", C.c_int64), ("max_groups", C.c_int64),
+                ("groups", Groups), ("topk_val", C.c_void_p), ("topk_row", C.c_void_p), ("topk_n", C.c_void_p)]
 
 
 class Tuning(C.Structure):
@@ -137,6 +157,16 @@ def lib():
         L.gq_batch_autotune.restype = st
         L.gq_batch_autotune.argtypes = [vp, C.POINTER(Instance), i32, C.c_char_p, C.POINTER(Tuning),
                                         C.POINTER(C.c_double), vp, sz, vp]
+        L.gq_server_create.restype = st
+        L.gq_server_create.argtypes = [i32, C.POINTER(ServerCfg), C.POINTER(vp)]
+        L.gq_server_submit.restype = st
+        L.gq_server_submit.argtypes = [vp, C.POINTER(Query), C.POINTER(C.c_uint64)]
+        L.gq_server_wait.restype = st
+        L.gq_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.gq_server_stats.restype = st
+        L.gq_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.gq_server_destroy.restype = None
+        L.gq_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -317,13 +347,14 @@ def alloc_groups(ctx: Context, capacity: int, key64: bool, key32: bool) -> Group
 
 def gq_groupby_agg(ctx: Context, qty, price, disc, n: int | None = None, n_dev=None, rowid=None, key64=None,
                    key64_by_rowid=False, key32=None, key32_by_rowid=False, rev_scale: int = 100,
-                   max_groups: int = 1024, out: GroupResult | None = None, ws=None) -> GroupResult:
+                   max_groups: int = 1024, out: GroupResult | None = None, ws=None, filter_col=None,
+                   filter_lo: int = 0, filter_hi: int = 0) -> GroupResult:
     """Exact group-by aggregate (see gq.h); returns device arrays + n_groups."""
     if n is None:
         n = rowid.numel() if rowid is not None else qty.numel()
     out = out if out is not None else alloc_groups(ctx, max_groups, key64 is not None, key32 is not None)
     gi = GroupbyIn(n, _ptr(n_dev), _ptr(rowid), _ptr(key64), int(key64_by_rowid), _ptr(key32), int(key32_by_rowid),
-                   _ptr(qty), _ptr(price), _ptr(disc), rev_scale)
+                   _ptr(qty), _ptr(price), _ptr(disc), rev_scale, _ptr(filter_col), filter_lo, filter_hi)
     go = Groups(_ptr(out.key64), _ptr(out.key32), _ptr(out.count), _ptr(out.sum_qty), _ptr(out.sum_rev_lo),
                 _ptr(out.sum_rev_hi), _ptr(out.avg_qty), _ptr(out.avg_rev), _ptr(out.n_groups), out.count.numel())
     need = lib().gq_groupby_workspace_bytes(n, max_groups, int(key64 is not None), int(key32 is not None))

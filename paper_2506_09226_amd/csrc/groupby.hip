@@ -53,6 +53,8 @@ struct gb_args {
     const int64_t *price;
     const int64_t *disc;
     int64_t rev_scale;
+    const int32_t *filter;          // nullable: rows need flo <= filter[v] < fhi
+    int64_t flo, fhi;
 };
 
 GQ_DEV int64_t eff_n(int64_t bound, const int64_t *n_dev)
@@ -66,6 +68,16 @@ GQ_DEV uint64_t gb_hash(int64_t k64, int32_t k32)
 {
     return gq_fmix64(static_cast<uint64_t>(k64) ^
                      (static_cast<uint64_t>(static_cast<uint32_t>(k32)) * 0x9E3779B97F4A7C15ull));
+}
+
+// Value row of input row j and whether it passes the optional row filter.
+GQ_DEV int64_t value_row(const gb_args &a, int64_t j) { return a.rowid ? static_cast<int64_t>(a.rowid[j]) : j; }
+
+GQ_DEV bool row_pass(const gb_args &a, int64_t v)
+{
+    if (!a.filter) return true;
+    const int64_t f = a.filter[v];
+    return a.flo <= f && f < a.fhi;
 }
 
 template <bool K64, bool K32>
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_small_kernel(gb_args a, gtable 
 #pragma unroll 4
         for (int c = 0; c < GB_ITEMS; ++c) {
             const int64_t j = j0 + c * GB_THREADS + threadIdx.x;
-            const bool active = j < n;
+            bool active = j < n && row_pass(a, value_row(a, j));
             gb_row<K64, K32> r{};
             if (active) r = load_row<K64, K32>(a, j);
             const uint64_t h = gb_hash(r.k64, r.k32);
@@ -373,7 +385,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int log2
 #pragma unroll 4
     for (int c = 0; c < items; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n) {
+        if (j < n && row_pass(a, value_row(a, j))) {
             int64_t k64;
             int32_t k32;
             load_key<K64, K32>(a, j, k64, k32);
@@ -407,11 +419,13 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int l
     __syncthreads();
     gb_rec<K64, K32> r[GB_ITEMS];
     uint32_t dst[GB_ITEMS];
+    bool keep[GB_ITEMS];
 #pragma unroll
     for (int c = 0; c < GB_ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n) {
-            const int64_t v = a.rowid ? static_cast<int64_t>(a.rowid[j]) : j;
+        const int64_t v = j < n ? value_row(a, j) : 0;
+        keep[c] = j < n && row_pass(a, v);
+        if (keep[c]) {
             int64_t k64 = 0;
             int32_t k32 = 0;
             if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
@@ -424,8 +438,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int l
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < GB_ITEMS; ++c) {
-        const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n) {
+        if (keep[c]) {
             const uint32_t b = dst[c] >> 20;
             uint4 *d = reinterpret_cast<uint4 *>(recs + static_cast<int64_t>(gstart[b]) + (dst[c] & 0xfffffu));
 #pragma unroll
@@ -463,11 +476,13 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
     __syncthreads();
     gb_rec<K64, K32> r[ITEMS];
     uint32_t pos[ITEMS];
+    bool keep[ITEMS];
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n) {
-            const int64_t v = a.rowid ? static_cast<int64_t>(a.rowid[j]) : j;
+        const int64_t v = j < n ? value_row(a, j) : 0;
+        keep[c] = j < n && row_pass(a, v);
+        if (keep[c]) {
             int64_t k64 = 0;
             int32_t k32 = 0;
             if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
@@ -497,8 +512,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
-        const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n) {
+        if (keep[c]) {
             const uint32_t b = pos[c] >> 16;
             const uint32_t q = lstart[b] + (pos[c] & 0xffffu);
             lbucket[q] = static_cast<uint16_t>(b);
@@ -507,8 +521,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
         }
     }
     __syncthreads();
-    const int64_t rem = n - base;
-    const uint32_t count = static_cast<uint32_t>(rem < TILE ? rem : TILE);
+    const uint32_t count = all;                      // rows of this tile that pass the filter
     uint4 *out = reinterpret_cast<uint4 *>(recs);
     for (uint32_t e = threadIdx.x; e < count * VECS; e += GB_THREADS) {
         const uint32_t q = e / VECS, x = e % VECS;
@@ -737,8 +750,8 @@ gq_status gq_groupby_agg(gq_ctx *ctx, const gq_groupby_in *in, int64_t max_group
     gb_ws w = gb_layout(c, pl, n, k64, k32);
     GQ_TRY(gq_zero(ctx, ws, w.zero_bytes / 4, s));
     GQ_TRY(gq_zero(ctx, out->n_groups, 2, s));
-    gb_args a{n,         in->n_dev, in->rowid, in->key64, in->key64_by_rowid, in->key32, in->key32_by_rowid,
-              in->qty,   in->price, in->disc,  in->rev_scale};
+    gb_args a{n,       in->n_dev, in->rowid, in->key64,     in->key64_by_rowid, in->key32, in->key32_by_rowid,
+              in->qty, in->price, in->disc,  in->rev_scale, in->filter,         in->filter_lo, in->filter_hi};
     if (k64 && k32) return run_groupby<true, true>(ctx, a, pl, w, *out, s);
     if (k64) return run_groupby<true, false>(ctx, a, pl, w, *out, s);
     if (k32) return run_groupby<false, true>(ctx, a, pl, w, *out, s);

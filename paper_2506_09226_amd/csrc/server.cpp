@@ -1,0 +1,313 @@
+// Request loop of the served form: footprint admission, continuous batching
+// of same-template queries into shared scans, batches in flight on several
+// HIP streams, completion by event polling, per-query latency.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gq_internal.h"
+#include "gq_serve.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct pending {
+    uint64_t ticket;
+    gq_serve_query q;
+    clk::time_point submitted;
+};
+
+struct done_state {
+    bool done = false;
+    gq_status status = GQ_OK;
+    double latency = 0.0;
+    clk::time_point submitted;
+};
+
+struct slot_t {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<uint64_t> tickets;
+    size_t off = 0, bytes = 0;
+    gq_status launch_status = GQ_OK;
+};
+
+// First-fit allocator over the pool (offsets, 256-byte granules).
+struct pool_alloc {
+    std::map<size_t, size_t> free_;       // offset -> size
+    void init(size_t bytes) { free_ = {{0, bytes & ~size_t(255)}}; }
+    bool take(size_t bytes, size_t *off)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void give(size_t off, size_t bytes)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct gq_server {
+    int device = 0;
+    gq_ctx *ctx = nullptr;
+    gq_serve_tables tables{};
+    char *pool = nullptr;
+    size_t pool_bytes = 0;
+    int max_batch = 1;
+    bool serial = false;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<pending> queue;
+    std::unordered_map<uint64_t, done_state> states;
+    std::vector<slot_t> slots;
+    pool_alloc alloc;
+    std::thread th;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    int64_t n_done = 0, n_batches = 0, max_seen = 0;
+
+    size_t bytes_of(const gq_serve_query *q, int nq) const
+    {
+        return serial ? gq_serve_single_bytes(tables, q[0]) : gq_serve_batch_bytes(tables, q, nq);
+    }
+    void loop();
+};
+
+void gq_server::loop()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        bool progress = false;
+        // retire finished batches
+        for (auto &sl : slots) {
+            if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+            const auto now = clk::now();
+            for (uint64_t t : sl.tickets) {
+                done_state &d = states[t];
+                d.done = true;
+                d.status = sl.launch_status;
+                d.latency = std::chrono::duration<double>(now - d.submitted).count();
+                ++n_done;
+            }
+            alloc.give(sl.off, sl.bytes);
+            sl.busy = false;
+            sl.tickets.clear();
+            progress = true;
+            cv_done.notify_all();
+        }
+        // admit and launch
+        bool any_busy = false;
+        for (auto &sl : slots) any_busy |= sl.busy;
+        for (auto &sl : slots) {
+            if (sl.busy || queue.empty()) continue;
+            if (serial && any_busy) break;
+            std::vector<size_t> pick;                     // indices into queue
+            const gq_serve_query &head = queue.front().q;
+            const int limit = serial ? 1 : max_batch;
+            for (size_t i = 0; i < queue.size() && static_cast<int>(pick.size()) < limit; ++i) {
+                const gq_serve_query &x = queue[i].q;
+                if (x.kind == head.kind && (x.kind != GQ_QUERY_FILTER_TOPK || x.k == head.k)) pick.push_back(i);
+            }
+            if (head.kind == GQ_QUERY_FILTER_TOPK && pick.size() > 8) pick.resize(8);
+            std::vector<gq_serve_query> qs;
+            size_t bytes = 0, off = 0;
+            while (!pick.empty()) {                       // largest prefix that fits the free pool
+                qs.clear();
+                for (size_t i : pick) qs.push_back(queue[i].q);
+                bytes = bytes_of(qs.data(), static_cast<int>(qs.size()));
+                if (alloc.take(bytes, &off)) break;
+                pick.pop_back();
+            }
+            if (pick.empty()) break;                       // wait for memory to free up
+            std::vector<uint64_t> tickets;
+            for (size_t k = pick.size(); k-- > 0;) {
+                tickets.push_back(queue[pick[k]].ticket);
+                queue.erase(queue.begin() + static_cast<long>(pick[k]));
+            }
+            sl.busy = true;
+            any_busy = true;
+            sl.tickets = tickets;
+            sl.off = off;
+            sl.bytes = bytes;
+            ++n_batches;
+            if (static_cast<int64_t>(qs.size()) > max_seen) max_seen = static_cast<int64_t>(qs.size());
+            lk.unlock();
+            gq_status st = serial ? gq_serve_single(ctx, tables, qs[0], pool + off, bytes, sl.stream)
+                                  : gq_serve_batch(ctx, tables, qs.data(), static_cast<int>(qs.size()), pool + off,
+                                                   bytes, sl.stream);
+            if (hipEventRecord(sl.done, sl.stream) != hipSuccess && st == GQ_OK) st = GQ_ERR_HIP;
+            lk.lock();
+            sl.launch_status = st;
+            progress = true;
+            if (serial) break;
+        }
+        bool busy = false;
+        for (auto &sl : slots) busy |= sl.busy;
+        if (stop && queue.empty() && !busy) break;
+        if (!progress) cv_work.wait_for(lk, std::chrono::microseconds(busy ? 20 : 2000));
+    }
+}
+
+extern "C" {
+
+gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out)
+{
+    if (!cfg || !out) return GQ_ERR_INVALID_ARG;
+    *out = nullptr;
+    const gq_server_tables &t = cfg->tables;
+    if (t.n < 0 || t.n > GQ_MAX_ROWS || (t.n > 0 && (!t.fk || !t.fk2 || !t.date || !t.qty || !t.price || !t.disc)) ||
+        !t.dim1_table || !t.dim2_table || !cfg->pool || cfg->pool_bytes < 4096 ||
+        reinterpret_cast<uintptr_t>(cfg->pool) % 256 != 0 || cfg->streams < 1 || cfg->streams > 8 ||
+        cfg->max_batch < 1 || cfg->max_batch > SV_MAX_BATCH)
+        return GQ_ERR_INVALID_ARG;
+    gq_server *s = new gq_server();
+    s->device = device;
+    if (gq_ctx_create(device, &s->ctx) != GQ_OK) {
+        delete s;
+        return GQ_ERR_HIP;
+    }
+    auto log2_of = [](size_t bytes) {
+        int L = 6;
+        while (L < 40 && 256 + (size_t(2) << L) * 16 <= bytes) ++L;
+        return L;
+    };
+    s->tables = {t.fk, t.fk2, t.date, t.qty, t.price, t.disc, t.n, t.dim1_table, t.dim2_table,
+                 log2_of(t.dim1_table_bytes), log2_of(t.dim2_table_bytes)};
+    s->pool = static_cast<char *>(cfg->pool);
+    s->pool_bytes = cfg->pool_bytes;
+    s->alloc.init(cfg->pool_bytes);
+    s->serial = cfg->serial != 0;
+    s->max_batch = s->serial ? 1 : cfg->max_batch;
+    (void)hipSetDevice(device);
+    s->slots.resize(s->serial ? 1 : cfg->streams);
+    for (auto &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            gq_server_destroy(s);
+            return GQ_ERR_HIP;
+        }
+    }
+    s->th = std::thread([s] { s->loop(); });
+    *out = s;
+    return GQ_OK;
+}
+
+gq_status gq_server_submit(gq_server *srv, const gq_query *q, uint64_t *ticket)
+{
+    if (!srv || !q || !ticket) return GQ_ERR_INVALID_ARG;
+    if (q->kind < GQ_QUERY_FILTER_AGG || q->kind > GQ_QUERY_FILTER_TOPK) return GQ_ERR_INVALID_ARG;
+    gq_serve_query x{};
+    x.kind = q->kind;
+    x.k = q->k;
+    x.date_hi = q->date_hi;
+    x.max_groups = q->max_groups;
+    x.out.groups = q->groups;
+    x.out.topk_val = q->topk_val;
+    x.out.topk_row = q->topk_row;
+    x.out.topk_n = q->topk_n;
+    if (x.kind == GQ_QUERY_FILTER_TOPK) {
+        if (x.k < 1 || x.k > 256) return GQ_ERR_UNSUPPORTED;
+        if (!x.out.topk_val || !x.out.topk_row || !x.out.topk_n) return GQ_ERR_INVALID_ARG;
+    } else {
+        const gq_groups &g = x.out.groups;
+        if (x.max_groups < 1 || x.max_groups > g.capacity || !g.count || !g.sum_qty || !g.sum_rev_lo ||
+            !g.sum_rev_hi || !g.avg_qty || !g.avg_rev || !g.n_groups)
+            return GQ_ERR_INVALID_ARG;
+        if (x.kind == GQ_QUERY_FILTER_AGG && !g.key64) return GQ_ERR_INVALID_ARG;
+        if (x.kind != GQ_QUERY_FILTER_AGG && !g.key32) return GQ_ERR_INVALID_ARG;
+        if (!srv->serial && x.kind != GQ_QUERY_JOIN_AGG && x.max_groups > SV_MAX_AGG_GROUPS)
+            return GQ_ERR_UNSUPPORTED;
+    }
+    if (srv->bytes_of(&x, 1) > srv->pool_bytes) return GQ_ERR_CAPACITY;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        *ticket = srv->next_ticket++;
+        done_state d;
+        d.submitted = clk::now();
+        srv->states[*ticket] = d;
+        srv->queue.push_back({*ticket, x, d.submitted});
+    }
+    srv->cv_work.notify_one();
+    return GQ_OK;
+}
+
+gq_status gq_server_wait(gq_server *srv, uint64_t ticket, gq_status *query_status, double *latency_s)
+{
+    if (!srv) return GQ_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->states.find(ticket);
+    if (it == srv->states.end()) return GQ_ERR_INVALID_ARG;
+    srv->cv_done.wait(lk, [&] { return srv->states[ticket].done; });
+    const done_state d = srv->states[ticket];
+    srv->states.erase(ticket);
+    if (query_status) *query_status = d.status;
+    if (latency_s) *latency_s = d.latency;
+    return GQ_OK;
+}
+
+gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen)
+{
+    if (!srv) return GQ_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (done) *done = srv->n_done;
+    if (batches) *batches = srv->n_batches;
+    if (max_batch_seen) *max_batch_seen = srv->max_seen;
+    return GQ_OK;
+}
+
+void gq_server_destroy(gq_server *srv)
+{
+    if (!srv) return;
+    if (srv->th.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stop = true;
+        }
+        srv->cv_work.notify_all();
+        srv->th.join();
+    }
+    for (auto &sl : srv->slots) {
+        if (sl.stream) {
+            (void)hipStreamSynchronize(sl.stream);
+            (void)hipStreamDestroy(sl.stream);
+        }
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (srv->ctx) gq_ctx_destroy(srv->ctx);
+    delete srv;
+}
+
+}  // extern "C"

@@ -311,3 +311,43 @@ def batch_tables(spec: BatchSpec, device="cpu", scale: float = 1.0):
         mo += m
         no += n
     return cols, layout
+
+
+# ----------------------------------------------------------------------------
+# Served workload: resident fact table with two foreign keys, two dimensions
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ServeSpec:
+    n: int = 1_600_000_000          # fact rows
+    m: int = 200_000_000            # rows of each dimension
+    seed: int = SEED_BASE + 4
+    code_range: int = 1_500_000     # dim1 attribute (join + aggregate groups)
+    attr_range: int = 25            # dim2 attribute (two-join + aggregate groups)
+
+
+def serve_tables(spec: ServeSpec, device="cpu"):
+    """(fact columns with fk and fk2, dim1, dim2).  dim2 uses seed + 1."""
+    fact = fact_table(FactSpec(spec.n, spec.m, spec.seed, m2=spec.m, seed2=spec.seed + 1), device=device)
+    dim1 = dim_table(spec.m, spec.seed, spec.code_range, device=device)
+    dim2 = dim_table(spec.m, spec.seed + 1, spec.attr_range, device=device)
+    return fact, dim1, dim2
+
+
+def serve_queries(count: int, seed: int, date_range: int = DATE_RANGE, kinds=(1, 2, 3, 4)):
+    """(kind, date_hi) per query: template uniform over `kinds`, selectivity
+    s uniform in [1%, 60%], date_hi = round(s * date_range)."""
+    rows = torch.arange(count, dtype=torch.int64)
+    ks = uniform_int(seed, 97, rows, 0, len(kinds) - 1).tolist()
+    ss = uniform_reals(count, 0.01, 0.60, seed, 96)
+    return [(kinds[k], int(round(s * date_range))) for k, s in zip(ks, ss)]
+
+
+def poisson_arrivals(count: int, qps: float, seed: int):
+    """Arrival times (s) of a Poisson process of rate qps (exponential gaps)."""
+    u = unit_float(seed, 95, torch.arange(count, dtype=torch.int64)).tolist()
+    t, out = 0.0, []
+    for x in u:
+        t += -math.log(1.0 - x) / qps
+        out.append(t)
+    return out

@@ -286,6 +286,20 @@ def test_groupby_key64_direct_no_rowid(ctx, max_groups):
     _check_groups(res, exp, True, False)
 
 
+@pytest.mark.parametrize("groups", [25, 5000])
+def test_groupby_row_filter(ctx, groups):
+    """Only rows whose value row passes filter_lo <= filter[v] < filter_hi."""
+    n = 200_000
+    rowid, key32, _, qty, price, disc = _gb_inputs(n, n, 55 + groups, groups)
+    fcol = rng(5).integers(0, 2557, size=n).astype(np.int32)
+    keep = np.nonzero(fcol[rowid] < 700)[0]
+    exp = oracle.groupby(len(keep), qty, price, disc, rowid=rowid[keep], key32=key32[keep])
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                            max_groups=groups, filter_col=dev(fcol), filter_lo=0, filter_hi=700)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, True)
+
+
 def test_groupby_no_key_and_empty(ctx):
     n = 10_000
     _, _, _, qty, price, disc = _gb_inputs(n, n, 4, 1)
