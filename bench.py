@@ -350,7 +350,11 @@ def bench_serve(args):
     torch.cuda.set_device(0)
     ctx = gq.Context(0)
     spec = synth.ServeSpec(n=args.serve_rows)
+    t_gen = time.perf_counter()
     fact, dim1, dim2 = synth.serve_tables(spec, device="cuda")
+    torch.cuda.synchronize()
+    print(f"# generated {spec.n:,} fact rows and 2 x {spec.m:,} dim rows in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
     t1 = gq.gq_join_build(ctx, dim1["key"], dim1["attr"])
     t2 = gq.gq_join_build(ctx, dim2["key"], dim2["attr"])
     torch.cuda.synchronize()
@@ -384,6 +388,7 @@ def bench_serve(args):
     warm = [ser.wait(ser.submit(q)) for q in qlist[:8]]
     iso = [ser.wait(ser.submit(q)).latency for q in qlist[:40]]
     t_bar = float(np.mean(iso))
+    print(f"# serial service time {t_bar * 1e3:.2f} ms over {len(iso)} queries", file=sys.stderr, flush=True)
     out_loads = {}
     results_equal = True
     for load in (0.8, 1.5):

@@ -406,11 +406,16 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const bt_inst *__rest
     int32_t *sp = reinterpret_cast<int32_t *>(lds_buf + BT_REGION_SLOTS * sizeof(unsigned long long));
     __shared__ int64_t s_item;
     __shared__ uint32_t s_last;
+    // Each pass starts with a barrier that every thread executes, so the
+    // thread-0 dequeue below is never fused with the thread-0 tail of the
+    // previous item (signal_done): fused, the two would form one divergent
+    // path around the loop head, and the other lanes could re-read the old
+    // item before thread 0 fetched the next one.
     while (true) {
+        __syncthreads();
         if (threadIdx.x == 0) s_item = static_cast<int64_t>(atomicAdd(work_ctr, 1u));
         __syncthreads();
-        const int64_t item = s_item;
-        __syncthreads();
+        const int64_t item = gq_uniform(s_item);
         if (item >= total_items) break;
         int lo = 0, hi = nsegs - 1;                        // last segment with first_item <= item
         while (lo < hi) {
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const bt_inst *__rest
                 s_last = (prev + 1 == static_cast<uint32_t>(I.probe_items)) ? 1u : 0u;
             }
             __syncthreads();
-            if (s_last) {
+            if (gq_uniform(s_last)) {
                 __threadfence();
                 emit_groups(I, status);
             }

@@ -34,6 +34,15 @@ GQ_DEV uint32_t gq_mbcnt(uint64_t mask)
 
 GQ_DEV uint64_t gq_ballot(bool p) { return __ballot(p); }
 
+// A value every lane of the wave holds (read from LDS after a barrier, say),
+// moved to a scalar register so that branches on it are scalar branches.
+GQ_DEV int64_t gq_uniform(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(static_cast<uint64_t>(v) >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 template <typename T>
 GQ_DEV T gq_wave_sum(T v)
 {

@@ -113,12 +113,15 @@ void gq_server::loop()
         bool progress = false;
         // retire finished batches
         for (auto &sl : slots) {
-            if (!sl.busy || hipEventQuery(sl.done) != hipSuccess) continue;
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            const gq_status st = q == hipSuccess ? sl.launch_status : GQ_ERR_HIP;   // a failed batch still retires
             const auto now = clk::now();
             for (uint64_t t : sl.tickets) {
                 done_state &d = states[t];
                 d.done = true;
-                d.status = sl.launch_status;
+                d.status = st;
                 d.latency = std::chrono::duration<double>(now - d.submitted).count();
                 ++n_done;
             }
@@ -251,7 +254,8 @@ gq_status gq_server_submit(gq_server *srv, const gq_query *q, uint64_t *ticket)
         if (!srv->serial && x.kind != GQ_QUERY_JOIN_AGG && x.max_groups > SV_MAX_AGG_GROUPS)
             return GQ_ERR_UNSUPPORTED;
     }
-    if (srv->bytes_of(&x, 1) > srv->pool_bytes) return GQ_ERR_CAPACITY;
+    // a query that could never be admitted, even into an idle pool, is refused
+    if (((srv->bytes_of(&x, 1) + 255) & ~size_t(255)) > (srv->pool_bytes & ~size_t(255))) return GQ_ERR_CAPACITY;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         *ticket = srv->next_ticket++;
