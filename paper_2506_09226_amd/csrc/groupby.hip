@@ -11,11 +11,12 @@
 //    workgroup); a finalize kernel compacts the global table.
 //
 //  large path: the rows are hash-partitioned by key into P buckets (hist ->
-//    scan -> LDS-staged scatter of key and value columns), chosen so that a
-//    bucket's groups fit one LDS table; one workgroup per bucket aggregates it
-//    in LDS and writes its groups out directly.  A bucket whose keys overflow
-//    its LDS table sends the extra keys to a global fallback table (correct,
-//    slower), compacted by the same finalize kernel.
+//    tile offsets -> LDS-staged scatter of narrow 16- or 24-byte records),
+//    P chosen so that a bucket's groups fit one LDS table; one workgroup per
+//    bucket aggregates it in LDS and writes its groups out directly.  A
+//    bucket whose keys overflow its LDS table sends the extra keys to a
+//    global fallback table (correct, slower), compacted by the same finalize
+//    kernel; rows too wide for a narrow record reach it through a side list.
 //
 // Table protocol (LDS and global alike): a per-slot state word 0 = empty,
 // 1 = being claimed, 2 = key published.  A lane claims a slot with a CAS
@@ -23,8 +24,6 @@
 // retries the same slot on its next pass of a wave-uniform loop, so the
 // claiming lane always finishes first.
 #include <algorithm>
-#include <cstdlib>
-#include <cstring>
 
 #include "gq_device.h"
 #include "gq_internal.h"
@@ -36,8 +35,7 @@ constexpr int GB_THREADS = 256;
 constexpr int GB_SMALL_SLOTS = 1024;
 constexpr int64_t GB_SMALL_GROUPS = 512;
 constexpr int GB_ITEMS = 16;
-constexpr int GB_TILE = GB_THREADS * GB_ITEMS;       // rows per hist/scatter tile
-constexpr int GB_MAX_LOG2P = 10;
+constexpr int GB_TILE = GB_THREADS * GB_ITEMS;       // rows per small-path pass
 constexpr int GB_BUCKET_THREADS = 1024;
 constexpr int GB_LDS_PROBES = 64;
 
@@ -141,7 +139,9 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     bool done = !active;
     while (__any(!done)) {
         if (!done) {
-            const uint32_t st = atomicCAS(&T.state[s], 0u, 1u);
+            // read first: most visits find a published key and need no atomic
+            uint32_t st = __hip_atomic_load(&T.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (st == 0u) st = atomicCAS(&T.state[s], 0u, 1u);
             if (st == 0u) {
                 if (K64) T.k64[s] = k64;
                 if (K32) T.k32[s] = k32;
@@ -204,7 +204,7 @@ GQ_DEV int64_t g_find(const gtable &g, bool active, uint64_t h, int64_t k64, int
                 __hip_atomic_store(&g.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 found = static_cast<int64_t>(s);
                 done = true;
-            } else if (st == 2u) {
+            } else if (st >= 2u) {                      // published (2) or taken (3)
                 (void)__hip_atomic_load(&g.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 const bool eq =
                     (!K64 || __hip_atomic_load(&g.k64[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k64) &&
@@ -232,6 +232,37 @@ GQ_DEV void g_add(const gtable &g, int64_t s, uint64_t cnt, uint64_t qty, gq_i12
         atomicAdd(reinterpret_cast<unsigned long long *>(&g.lo[s]), static_cast<unsigned long long>(rev.lo));
     const int64_t hadd = rev.hi + ((old + rev.lo < old) ? 1 : 0);
     if (hadd) atomicAdd(reinterpret_cast<unsigned long long *>(&g.hi[s]), static_cast<unsigned long long>(hadd));
+}
+
+// Find-only lookup in the global table (wave-uniform loop); -1 if absent.
+template <bool K64, bool K32>
+GQ_DEV int64_t g_lookup(const gtable &g, bool active, uint64_t h, int64_t k64, int32_t k32)
+{
+    uint64_t s = h & g.mask;
+    uint64_t probes = 0;
+    int64_t found = -1;
+    bool done = !active;
+    while (__any(!done)) {
+        if (!done) {
+            const uint32_t st = __hip_atomic_load(&g.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (st == 0u) {
+                done = true;
+            } else if (st >= 2u) {
+                const bool eq =
+                    (!K64 || __hip_atomic_load(&g.k64[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k64) &&
+                    (!K32 || __hip_atomic_load(&g.k32[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == k32);
+                if (eq) {
+                    found = static_cast<int64_t>(s);
+                    done = true;
+                } else if (++probes > g.mask) {
+                    done = true;
+                } else {
+                    s = (s + 1) & g.mask;
+                }
+            }
+        }
+    }
+    return found;
 }
 
 // Append one finished group to the output (idx from the caller's counter).
@@ -316,50 +347,74 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 
 // -------------------------------------------------------------- large path
 //
-// Partitioned rows are AoS records of 32 bytes (key64 or key32, qty, price,
-// disc) or 64 bytes (composite key), written whole from registers: every
-// record covers whole 32-byte memory sectors, so scattered short runs cost no
-// partial-sector write amplification and need no LDS staging.
-// A record is stored and loaded as whole 16-byte vectors (padding included),
-// so each 32-byte sector is written completely by one store pair.
+// Rows are hash-partitioned by key into P buckets (any P in [2, GB_MAX_P]:
+// the high 32 hash bits scaled to P), then one workgroup per bucket
+// aggregates it in an LDS table.  A partitioned row is a narrow record of
+// 8-byte words holding the key, qty as int32 and the revenue
+// price * (rev_scale - disc) as int64:
+//   key32 only       2 words  {k32 | qty32, rev64}
+//   key64 (+ key32)  3 words  {k64, k32 | qty32, rev64}
+// A row whose qty or revenue needs more bits (a wide row) is written with
+// qty 0 and revenue 0, so it still counts one row in its bucket, and its row
+// index goes to a side list.  A side kernel adds the full values of those
+// rows to the global table with a count of 0; a bucket whose LDS group also
+// has an entry there folds it in when it writes the group out and marks the
+// entry taken (state 3).  With no wide rows the side list stays empty.
+constexpr int GB_MAX_P = 1024;
+constexpr int64_t GB_CUS = 256;                     // compute units of the MI355X
+constexpr int GB_BUCKET_ITEMS = 4;
+
 template <bool K64, bool K32>
-struct gb_rec {
-    static constexpr int VECS = (K64 && K32) ? 4 : 2;   // 16-byte vectors per record
-    uint4 v[VECS];
+struct gb_fmt {
+    static constexpr int WORDS = K64 ? 3 : 2;
+    static constexpr int ITEMS = K64 ? 8 : 16;           // rows per thread of a hist/scatter tile
+    static constexpr int TILE = GB_THREADS * ITEMS;
 };
 
-template <bool K64, bool K32>
-GQ_DEV gb_rec<K64, K32> make_rec(int64_t k64, int32_t k32, int64_t qty, int64_t price, int64_t disc)
+GQ_DEV uint32_t gb_bucket(uint64_t h, int P)
 {
-    gb_rec<K64, K32> r;
-    const uint64_t kw = K64 ? static_cast<uint64_t>(k64) : static_cast<uint64_t>(static_cast<uint32_t>(k32));
-    r.v[0] = make_uint4(static_cast<uint32_t>(kw), static_cast<uint32_t>(kw >> 32), static_cast<uint32_t>(qty),
-                        static_cast<uint32_t>(static_cast<uint64_t>(qty) >> 32));
-    r.v[1] = make_uint4(static_cast<uint32_t>(price), static_cast<uint32_t>(static_cast<uint64_t>(price) >> 32),
-                        static_cast<uint32_t>(disc), static_cast<uint32_t>(static_cast<uint64_t>(disc) >> 32));
-    if constexpr (K64 && K32) {
-        r.v[2] = make_uint4(static_cast<uint32_t>(k32), 0u, 0u, 0u);
-        r.v[3] = make_uint4(0u, 0u, 0u, 0u);
+    return static_cast<uint32_t>(((h >> 32) * static_cast<uint64_t>(P)) >> 32);
+}
+
+GQ_DEV uint64_t pack2(uint32_t lo, uint32_t hi) { return (static_cast<uint64_t>(hi) << 32) | lo; }
+
+GQ_DEV bool is_narrow(int64_t qty, const gq_i128 &rev)
+{
+    return qty == static_cast<int64_t>(static_cast<int32_t>(qty)) &&
+           rev.hi == (static_cast<int64_t>(rev.lo) >> 63);
+}
+
+template <bool K64, bool K32>
+GQ_DEV void make_words(uint64_t *w, int64_t k64, int32_t k32, int32_t q32, int64_t rev)
+{
+    if constexpr (!K64) {
+        w[0] = pack2(static_cast<uint32_t>(k32), static_cast<uint32_t>(q32));
+        w[1] = static_cast<uint64_t>(rev);
+    } else {
+        w[0] = static_cast<uint64_t>(k64);
+        w[1] = pack2(K32 ? static_cast<uint32_t>(k32) : 0u, static_cast<uint32_t>(q32));
+        w[2] = static_cast<uint64_t>(rev);
     }
-    return r;
-}
-
-GQ_DEV int64_t u64_of(uint32_t lo, uint32_t hi)
-{
-    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 template <bool K64, bool K32>
-GQ_DEV void read_rec(const gb_rec<K64, K32> *recs, int64_t i, int64_t &k64, int32_t &k32, int64_t &qty,
-                     int64_t &price, int64_t &disc)
+GQ_DEV void read_words(const uint64_t *__restrict__ recs, int64_t i, int64_t &k64, int32_t &k32, int64_t &qty,
+                       int64_t &rev)
 {
-    const uint4 *p = reinterpret_cast<const uint4 *>(recs + i);
-    const uint4 a = p[0], b = p[1];
-    k64 = K64 ? u64_of(a.x, a.y) : 0;
-    k32 = K32 ? static_cast<int32_t>(K64 ? p[2].x : a.x) : 0;
-    qty = u64_of(a.z, a.w);
-    price = u64_of(b.x, b.y);
-    disc = u64_of(b.z, b.w);
+    if constexpr (!K64) {
+        const uint4 v = reinterpret_cast<const uint4 *>(recs)[i];
+        k64 = 0;
+        k32 = static_cast<int32_t>(v.x);
+        qty = static_cast<int32_t>(v.y);
+        rev = static_cast<int64_t>(pack2(v.z, v.w));
+    } else {
+        const uint64_t *p = recs + i * 3;
+        const uint64_t b = p[1];
+        k64 = static_cast<int64_t>(p[0]);
+        k32 = K32 ? static_cast<int32_t>(static_cast<uint32_t>(b)) : 0;
+        qty = static_cast<int32_t>(static_cast<uint32_t>(b >> 32));
+        rev = static_cast<int64_t>(p[2]);
+    }
 }
 
 template <bool K64, bool K32>
@@ -373,108 +428,51 @@ GQ_DEV void load_key(const gb_args &a, int64_t j, int64_t &k64, int32_t &k32)
 
 // LDS histogram of one tile of rows, written as the tile's row hist[t * P + b].
 template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int log2p, int items,
-                                                             uint32_t *__restrict__ hist)
+__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t h[1 << GB_MAX_LOG2P];
-    const int P = 1 << log2p;
+    constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
+    __shared__ uint32_t h[GB_MAX_P];
     for (int i = threadIdx.x; i < P; i += GB_THREADS) h[i] = 0;
     __syncthreads();
     const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * GB_THREADS * items;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * gb_fmt<K64, K32>::TILE;
 #pragma unroll 4
-    for (int c = 0; c < items; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int64_t j = base + c * GB_THREADS + threadIdx.x;
         if (j < n && row_pass(a, value_row(a, j))) {
             int64_t k64;
             int32_t k32;
             load_key<K64, K32>(a, j, k64, k32);
-            atomicAdd(&h[static_cast<uint32_t>(gb_hash(k64, k32) >> (64 - log2p))], 1u);
+            atomicAdd(&h[gb_bucket(gb_hash(k64, k32), P)], 1u);
         }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < P; b += GB_THREADS) hist[static_cast<int64_t>(blockIdx.x) * P + b] = h[b];
 }
 
-// Scatter rows to their buckets: rank inside (bucket, tile) by an LDS atomic
-// (order inside a bucket is irrelevant to sums), then write each record whole
-// to gofs[b, t] + rank.
+// Scatter one tile: rank each row inside its bucket with an LDS atomic (the
+// order inside a bucket does not matter to sums), stage the records in LDS in
+// bucket order, then write them out as contiguous runs starting at the
+// tile's offset gofs[t * P + b] in each bucket.
 template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int log2p,
-                                                                const uint32_t *__restrict__ gofs, int64_t ntiles,
-                                                                gb_rec<K64, K32> *__restrict__ recs)
+__global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P, const uint32_t *__restrict__ gofs,
+                                                                uint64_t *__restrict__ recs,
+                                                                uint32_t *__restrict__ side, uint32_t *side_cnt)
 {
-    constexpr int PMAX = 1 << GB_MAX_LOG2P;
-    __shared__ uint32_t lcnt[PMAX];
-    __shared__ uint32_t gstart[PMAX];
-    const int P = 1 << log2p;
-    const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t base = static_cast<int64_t>(tile) * GB_TILE;
-    if (base >= n) return;                          // whole block: uniform
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) {
-        lcnt[b] = 0;
-        gstart[b] = gofs[static_cast<int64_t>(tile) * P + b];
-    }
-    __syncthreads();
-    gb_rec<K64, K32> r[GB_ITEMS];
-    uint32_t dst[GB_ITEMS];
-    bool keep[GB_ITEMS];
-#pragma unroll
-    for (int c = 0; c < GB_ITEMS; ++c) {
-        const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        const int64_t v = j < n ? value_row(a, j) : 0;
-        keep[c] = j < n && row_pass(a, v);
-        if (keep[c]) {
-            int64_t k64 = 0;
-            int32_t k32 = 0;
-            if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
-            if (K32) k32 = a.key32[a.key32_by_rowid ? v : j];
-            r[c] = make_rec<K64, K32>(k64, k32, a.qty[v], a.price[v], a.disc[v]);
-            const uint32_t b = static_cast<uint32_t>(gb_hash(k64, k32) >> (64 - log2p));
-            dst[c] = (b << 20) | atomicAdd(&lcnt[b], 1u);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < GB_ITEMS; ++c) {
-        if (keep[c]) {
-            const uint32_t b = dst[c] >> 20;
-            uint4 *d = reinterpret_cast<uint4 *>(recs + static_cast<int64_t>(gstart[b]) + (dst[c] & 0xfffffu));
-#pragma unroll
-            for (int q = 0; q < gb_rec<K64, K32>::VECS; ++q) d[q] = r[c].v[q];
-        }
-    }
-}
-
-// Staged variant: records are placed in LDS in bucket order and written out
-// as contiguous runs (consecutive threads store consecutive 16-byte vectors).
-constexpr int GB_STAGED_ITEMS = 8;                  // 2048-row tiles: 64 KiB of 32-byte records
-
-template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a, int log2p,
-                                                                       const uint32_t *__restrict__ gofs,
-                                                                       int64_t ntiles,
-                                                                       gb_rec<K64, K32> *__restrict__ recs)
-{
-    constexpr int PMAX = 1 << GB_MAX_LOG2P;
-    constexpr int ITEMS = (K64 && K32) ? GB_STAGED_ITEMS / 2 : GB_STAGED_ITEMS;
-    constexpr int TILE = GB_THREADS * ITEMS;
-    constexpr int VECS = gb_rec<K64, K32>::VECS;
-    __shared__ uint32_t lcnt[PMAX];
-    __shared__ uint32_t lstart[PMAX];
-    __shared__ uint32_t gstart[PMAX];
+    constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
+    constexpr int TILE = gb_fmt<K64, K32>::TILE;
+    constexpr int W = gb_fmt<K64, K32>::WORDS;
+    __shared__ uint32_t lpos[GB_MAX_P];          // counts -> local starts -> (global - local) starts
     __shared__ uint32_t scan_smem[GB_THREADS / 64];
     __shared__ uint16_t lbucket[TILE];
-    __shared__ uint4 stage[TILE * VECS];
-    const int P = 1 << log2p;
+    __shared__ uint64_t stage[TILE * W];
     const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
     const int64_t n = eff_n(a.n_bound, a.n_dev);
     const int64_t base = static_cast<int64_t>(tile) * TILE;
     if (base >= n) return;                          // whole block: uniform
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) lcnt[b] = 0;
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = 0;
     __syncthreads();
-    gb_rec<K64, K32> r[ITEMS];
+    uint64_t w[ITEMS][W];
     uint32_t pos[ITEMS];
     bool keep[ITEMS];
 #pragma unroll
@@ -483,13 +481,16 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
         const int64_t v = j < n ? value_row(a, j) : 0;
         keep[c] = j < n && row_pass(a, v);
         if (keep[c]) {
-            int64_t k64 = 0;
-            int32_t k32 = 0;
-            if (K64) k64 = a.key64[a.key64_by_rowid ? v : j];
-            if (K32) k32 = a.key32[a.key32_by_rowid ? v : j];
-            r[c] = make_rec<K64, K32>(k64, k32, a.qty[v], a.price[v], a.disc[v]);
-            const uint32_t b = static_cast<uint32_t>(gb_hash(k64, k32) >> (64 - log2p));
-            pos[c] = (b << 16) | atomicAdd(&lcnt[b], 1u);
+            const int64_t k64 = K64 ? a.key64[a.key64_by_rowid ? v : j] : 0;
+            const int32_t k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
+            const int64_t qty = a.qty[v];
+            const gq_i128 rev = gq_revenue(a.price[v], a.rev_scale, a.disc[v]);
+            const bool nar = is_narrow(qty, rev);
+            if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
+            make_words<K64, K32>(w[c], k64, k32, nar ? static_cast<int32_t>(qty) : 0,
+                                 nar ? static_cast<int64_t>(rev.lo) : 0);
+            const uint32_t b = gb_bucket(gb_hash(k64, k32), P);
+            pos[c] = (b << 16) | atomicAdd(&lpos[b], 1u);
         }
     }
     __syncthreads();
@@ -497,16 +498,16 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
     uint32_t local = 0;
     for (int i = 0; i < per; ++i) {
         const int b = threadIdx.x * per + i;
-        if (b < P) local += lcnt[b];
+        if (b < P) local += lpos[b];
     }
     uint32_t all;
     uint32_t run = gq_block_exclusive_scan<GB_THREADS>(local, &all, scan_smem);
     for (int i = 0; i < per; ++i) {
         const int b = threadIdx.x * per + i;
         if (b < P) {
-            lstart[b] = run;
-            run += lcnt[b];
-            gstart[b] = gofs[static_cast<int64_t>(tile) * P + b];
+            const uint32_t c = lpos[b];
+            lpos[b] = run;
+            run += c;
         }
     }
     __syncthreads();
@@ -514,37 +515,39 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_staged_kernel(gb_args a
     for (int c = 0; c < ITEMS; ++c) {
         if (keep[c]) {
             const uint32_t b = pos[c] >> 16;
-            const uint32_t q = lstart[b] + (pos[c] & 0xffffu);
+            const uint32_t q = lpos[b] + (pos[c] & 0xffffu);
             lbucket[q] = static_cast<uint16_t>(b);
 #pragma unroll
-            for (int x = 0; x < VECS; ++x) stage[q * VECS + x] = r[c].v[x];
+            for (int x = 0; x < W; ++x) stage[q * W + x] = w[c][x];
         }
     }
     __syncthreads();
-    const uint32_t count = all;                      // rows of this tile that pass the filter
-    uint4 *out = reinterpret_cast<uint4 *>(recs);
-    for (uint32_t e = threadIdx.x; e < count * VECS; e += GB_THREADS) {
-        const uint32_t q = e / VECS, x = e % VECS;
-        const uint32_t b = lbucket[q];
-        out[(static_cast<int64_t>(gstart[b]) + (q - lstart[b])) * VECS + x] = stage[e];
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = gofs[static_cast<int64_t>(tile) * P + b] - lpos[b];
+    __syncthreads();
+    const uint32_t words = all * W;                  // rows of this tile that pass the filter
+    for (uint32_t e = threadIdx.x; e < words; e += GB_THREADS) {
+        const uint32_t q = e / W, x = e - q * W;
+        const uint32_t row = q + lpos[lbucket[q]];  // global row position in the bucket array
+        recs[static_cast<int64_t>(row) * W + x] = stage[e];
     }
 }
 
-// Which scatter: "direct" (records written from registers) or "staged" (LDS,
-// contiguous runs).  GQ_GROUPBY_SCATTER overrides the default.
-bool gb_staged()
+// Full values of the wide rows into the global table (count 0: their rows
+// were counted by their narrow records).
+template <bool K64, bool K32>
+__global__ __launch_bounds__(256) void gb_side_kernel(gb_args a, const uint32_t *__restrict__ side,
+                                                      const uint32_t *side_cnt, gtable g, uint32_t *status)
 {
-    static const bool v = [] {
-        const char *e = getenv("GQ_GROUPBY_SCATTER");
-        return !(e && strcmp(e, "direct") == 0);
-    }();
-    return v;
-}
-
-int gb_items(bool k64, bool k32)
-{
-    if (!gb_staged()) return GB_ITEMS;
-    return (k64 && k32) ? GB_STAGED_ITEMS / 2 : GB_STAGED_ITEMS;
+    const uint32_t cnt = *side_cnt;
+    for (uint32_t i0 = blockIdx.x * 256u; i0 < cnt; i0 += gridDim.x * 256u) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool active = i < cnt;
+        gb_row<K64, K32> r{};
+        if (active) r = load_row<K64, K32>(a, side[i]);
+        const uint64_t h = gb_hash(r.k64, r.k32);
+        const int64_t gs = g_find<K64, K32>(g, active, h, r.k64, r.k32, status);
+        if (active && gs >= 0) g_add(g, gs, 0u, static_cast<uint64_t>(r.qty), r.rev);
+    }
 }
 
 template <bool K64, bool K32>
@@ -553,10 +556,10 @@ struct bucket_slots {
 };
 
 template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const gb_rec<K64, K32> *__restrict__ recs,
+__global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint64_t *__restrict__ recs,
                                                                       const uint32_t *__restrict__ start,
-                                                                      int64_t rev_scale,
-                                                                      gtable g, gq_groups out, uint32_t *status)
+                                                                      const uint32_t *side_cnt, gtable g,
+                                                                      gq_groups out, uint32_t *status)
 {
     constexpr int SLOTS = bucket_slots<K64, K32>::value;
     __shared__ lds_table<SLOTS, K64, K32> T;
@@ -566,23 +569,31 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const gb_r
     const int64_t r0 = start[b], r1 = start[b + 1];
     lds_init(T);
     __syncthreads();
-    for (int64_t i0 = r0; i0 < r1; i0 += GB_BUCKET_THREADS) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool active = i < r1;
-        int64_t k64 = 0, q = 0;
-        int32_t k32 = 0;
-        gq_i128 rev{0, 0};
-        if (active) {
-            int64_t price, disc;
-            read_rec<K64, K32>(recs, i, k64, k32, q, price, disc);
-            rev = gq_revenue(price, rev_scale, disc);
+    constexpr int STEP = GB_BUCKET_THREADS * GB_BUCKET_ITEMS;
+    for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
+        int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
+        int32_t k32[GB_BUCKET_ITEMS];
+#pragma unroll
+        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+            const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
+            k64[c] = q[c] = rv[c] = 0;
+            k32[c] = 0;
+            if (i < r1) read_words<K64, K32>(recs, i, k64[c], k32[c], q[c], rv[c]);
         }
-        const uint64_t h = gb_hash(k64, k32);
-        const int s = lds_find(T, active, h, k64, k32);
-        if (active && s >= 0) lds_add(T, s, 1u, static_cast<uint64_t>(q), rev);
-        const bool spill = active && s < 0;
-        const int64_t gs = g_find<K64, K32>(g, spill, h, k64, k32, status);
-        if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q), rev);
+#pragma unroll
+        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+            const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
+            const bool active = i < r1;
+            gq_i128 rev;
+            rev.lo = static_cast<uint64_t>(rv[c]);
+            rev.hi = rv[c] >> 63;
+            const uint64_t h = gb_hash(k64[c], k32[c]);
+            const int s = lds_find(T, active, h, k64[c], k32[c]);
+            if (active && s >= 0) lds_add(T, s, 1u, static_cast<uint64_t>(q[c]), rev);
+            const bool spill = active && s < 0;
+            const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
+            if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
+        }
     }
     __syncthreads();
     // emit: each thread owns SLOTS / GB_BUCKET_THREADS consecutive slots
@@ -597,13 +608,29 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const gb_r
                                    static_cast<unsigned long long>(total))
                        : 0ull;
     __syncthreads();
+    const bool merge = *side_cnt != 0u;            // same value for every thread
     int64_t idx = static_cast<int64_t>(s_base) + pre;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int s = threadIdx.x * PER + i;
-        if (T.state[s] == 2u) {
-            emit_group(out, idx, K64 ? T.k64[s] : 0, K32 ? T.k32[s] : 0, T.cnt[s], T.sq[s], T.lo[s], T.hi[s],
-                       status);
+        const bool occ = T.state[s] == 2u;
+        const int64_t k64 = (K64 && occ) ? T.k64[s] : 0;
+        const int32_t k32 = (K32 && occ) ? T.k32[s] : 0;
+        uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0, lo = occ ? T.lo[s] : 0;
+        int64_t hi = occ ? T.hi[s] : 0;
+        if (merge) {
+            const int64_t gs = g_lookup<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32);
+            if (occ && gs >= 0) {
+                cnt += g.cnt[gs];
+                sq += g.sq[gs];
+                const uint64_t l2 = lo + g.lo[gs];
+                hi += g.hi[gs] + (l2 < lo ? 1 : 0);
+                lo = l2;
+                __hip_atomic_store(&g.state[gs], 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (occ) {
+            emit_group(out, idx, k64, k32, cnt, sq, lo, hi, status);
             ++idx;
         }
     }
@@ -619,37 +646,42 @@ uint64_t next_pow2(uint64_t x)
 
 struct gb_plan {
     bool small;
-    int log2p;
-    int items;              // rows per thread of a hist/scatter tile
-    int64_t ntiles;
+    int P;                  // buckets of the large path
+    int64_t ntiles;         // hist/scatter tiles
+    int words;              // 8-byte words per partitioned record
     uint64_t gslots;
 };
 
 gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
 {
+    (void)k32;
     gb_plan pl{};
     pl.small = max_groups <= GB_SMALL_GROUPS;
     pl.gslots = next_pow2(static_cast<uint64_t>(max_groups > 32 ? 2 * max_groups : 64));
-    pl.items = gb_items(k64, k32);
-    const int64_t tile = static_cast<int64_t>(GB_THREADS) * pl.items;
+    const int64_t tile = static_cast<int64_t>(GB_THREADS) * (k64 ? 8 : 16);
     pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
+    pl.words = k64 ? 3 : 2;
     if (!pl.small) {
-        const int64_t per_bucket = (k64 ? 3072 : 4096) / 2;
-        const uint64_t want = static_cast<uint64_t>((max_groups + per_bucket - 1) / per_bucket);
-        int l = 1;
-        while ((1ull << l) < want && l < GB_MAX_LOG2P) ++l;
-        pl.log2p = l;
+        // about 60% of a bucket's LDS table for the expected groups
+        const int64_t per_bucket = (k64 ? 3072 : 4096) * 6 / 10;
+        int64_t P = (max_groups + per_bucket - 1) / per_bucket;
+        // one 1024-thread workgroup per bucket and one per CU at a time: a
+        // whole number of rounds over the CUs leaves no idle tail
+        if (P > GB_CUS) P = (P + GB_CUS - 1) / GB_CUS * GB_CUS;
+        pl.P = static_cast<int>(std::min<int64_t>(std::max<int64_t>(P, 2), GB_MAX_P));
     }
     return pl;
 }
 
 struct gb_ws {
     gtable g;
+    uint32_t *side_cnt;
     uint32_t *hist;
     uint32_t *start;
     void *scan_ws;
-    void *recs;             // partitioned rows, 32- or 64-byte records
-    size_t zero_bytes;      // prefix of the workspace to clear (the table)
+    uint64_t *recs;         // partitioned rows, narrow records
+    uint32_t *side;         // row indices of wide rows
+    size_t zero_bytes;      // prefix of the workspace to clear (table, side count)
 };
 
 gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
@@ -664,14 +696,15 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     w.g.lo = c.take<uint64_t>(S);
     w.g.hi = c.take<int64_t>(S);
     w.g.mask = S - 1;
+    w.side_cnt = c.take<uint32_t>(64);
     w.zero_bytes = c.off;
     if (!pl.small) {
-        const int64_t cells = pl.ntiles << pl.log2p;
-        w.hist = c.take<uint32_t>(static_cast<size_t>(cells));
-        w.start = c.take<uint32_t>((size_t(1) << pl.log2p) + 1);
-        w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, 1 << pl.log2p));
         const size_t rows = static_cast<size_t>(n > 0 ? n : 1);
-        w.recs = c.take<char>(rows * ((k64 && k32) ? 64 : 32));
+        w.hist = c.take<uint32_t>(static_cast<size_t>(pl.ntiles) * static_cast<size_t>(pl.P));
+        w.start = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
+        w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, pl.P));
+        w.recs = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
+        w.side = c.take<uint32_t>(rows);
     }
     return w;
 }
@@ -693,20 +726,18 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                          w.g, out, ctx->status_dev);
     }
     const uint32_t grid = static_cast<uint32_t>(pl.ntiles);
-    const int P = 1 << pl.log2p;
-    GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a,
-                     pl.log2p, pl.items, w.hist));
-    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, P, w.start, w.scan_ws, s, "gq_groupby_scan"));
-    auto *recs = static_cast<gb_rec<K64, K32> *>(w.recs);
-    if (pl.items == GB_ITEMS)
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s,
-                         a, pl.log2p, static_cast<const uint32_t *>(w.hist), pl.ntiles, recs));
-    else
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_staged_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS),
-                         0, s, a, pl.log2p, static_cast<const uint32_t *>(w.hist), pl.ntiles, recs));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(P)),
-                     dim3(GB_BUCKET_THREADS), 0, s, static_cast<const gb_rec<K64, K32> *>(recs),
-                     static_cast<const uint32_t *>(w.start), a.rev_scale, w.g, out, ctx->status_dev));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a, pl.P,
+                     w.hist));
+    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, pl.P, w.start, w.scan_ws, s, "gq_groupby_scan"));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a,
+                     pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
+                     static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
+                     ctx->status_dev));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(pl.P)),
+                     dim3(GB_BUCKET_THREADS), 0, s, static_cast<const uint64_t *>(w.recs),
+                     static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.side_cnt), w.g, out,
+                     ctx->status_dev));
     return gq_launch(ctx, "gq_groupby_emit", gb_table_emit_kernel<K64, K32>, dim3(emit_blocks), dim3(256), 0, s, w.g,
                      out, ctx->status_dev);
 }

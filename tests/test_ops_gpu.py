@@ -338,7 +338,7 @@ def test_groupby_large_path_overflowing_buckets(ctx):
     cand = r.integers(0, 1 << 31, size=4_000_000).astype(np.int64)
     with np.errstate(over="ignore"):
         h = _fmix64_np(cand.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15))
-    hot = np.unique(cand[(h >> np.uint64(57)) == 0])[:9000]          # top 7 bits 0: bucket 0 of 128
+    hot = np.unique(cand[(h >> np.uint64(57)) == 0])[:9000]          # top 7 bits 0: bucket 0 while P <= 128
     assert len(hot) == 9000
     n = 400_000
     other = r.integers(0, 1 << 31, size=50_000)
@@ -354,6 +354,57 @@ def test_groupby_large_path_overflowing_buckets(ctx):
                             max_groups=250_000)
     assert ctx.status() == gq.GQ_OK
     _check_groups(res, exp, False, True)
+
+
+def _hot_keys(r, count):
+    """int32 keys whose group hash has its top 8 bits zero: with P <= 256
+    buckets they all land in bucket 0 and overflow its LDS table."""
+    cand = r.integers(0, 1 << 31, size=4_000_000).astype(np.int64)
+    with np.errstate(over="ignore"):
+        h = _fmix64_np(cand.astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15))
+    hot = np.unique(cand[(h >> np.uint64(56)) == 0])[:count]
+    assert len(hot) == count
+    return hot
+
+
+@pytest.mark.parametrize("composite", [False, True])
+@pytest.mark.parametrize("overflow", [False, True])
+def test_groupby_large_path_wide_rows(ctx, composite, overflow):
+    """Rows whose qty needs more than 32 bits or whose revenue needs more than
+    64 bits mix with ordinary rows in the same groups; some groups hold only
+    such rows; with overflow, thousands of keys share one bucket and spill to
+    the global table.  Every sum stays exact."""
+    r = rng(61 + int(composite) + 2 * int(overflow))
+    n = nv = 300_000
+    keys = r.integers(0, 1 << 31, size=6000)
+    if overflow:
+        keys = np.concatenate([keys, _hot_keys(r, 9000)])
+    keys = np.unique(keys).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    wide = np.nonzero(r.random(nv) < 0.05)[0]
+    half = len(wide) // 2
+    qty[wide[:half]] = r.integers(1 << 33, 1 << 40, size=half) * np.where(r.random(half) < 0.3, -1, 1)
+    price[wide[half:]] = ((1 << 62) - r.integers(0, 1000, size=len(wide) - half)) * \
+        np.where(r.random(len(wide) - half) < 0.5, -1, 1)
+    key32 = keys[r.integers(0, len(keys), size=n)]
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    only_wide = np.isin(key32, keys[:50])                       # these groups see wide rows only
+    rowid[only_wide] = wide[r.integers(0, len(wide), size=int(only_wide.sum()))]
+    max_groups = 250_000 if overflow else 8000
+    if composite:
+        key64 = np.where(np.isin(key32, keys[:3000]), 0, key32.astype(np.int64) * 7 + 1).astype(np.int64)
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                                key32=dev(key32), max_groups=max_groups)
+    else:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                                max_groups=max_groups)
+    assert ctx.status() == gq.GQ_OK
+    assert any(abs(v) >= 1 << 63 for v in oracle.sum_rev_int(exp))
+    _check_groups(res, exp, composite, True)
 
 
 def test_groupby_repeatable(ctx):
