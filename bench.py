@@ -51,7 +51,7 @@ OP_KERNELS = {
     "join_build": ["gq_join_build_init", "gq_join_build_insert", "gq_join_build_part_hist",
                    "gq_join_build_part_scan", "gq_join_build_part_offsets", "gq_join_build_part_scatter",
                    "gq_join_build_bounds", "gq_join_build_regions", "gq_join_build_overflow"],
-    "join_probe": ["gq_join_probe"],
+    "join_probe": ["gq_join_probe", "gq_join_probe_split", "gq_join_probe_lists"],
     "groupby": ["gq_groupby_hist", "gq_groupby_scan", "gq_groupby_scatter", "gq_groupby_side", "gq_groupby_bucket",
                 "gq_groupby_emit", "gq_groupby_local"],
     "topk": ["gq_topk_local", "gq_topk_merge"],
@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16_777_216)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--probe", default="auto", choices=["auto", "ordered", "partitioned"],
+                    help="join probe form (auto: partitioned when the table exceeds the L2 caches)")
     ap.add_argument("--no-partition", action="store_true",
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -167,7 +169,7 @@ def main():
     print(f"# generated {w.fact.n:,} x {w.dim_m:,} rows in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
           flush=True)
     pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=w.log2_fanout, topk=100,
-                       partition=not args.no_partition)
+                       partition=not args.no_partition, probe=args.probe)
 
     for _ in range(args.warmup):
         pl.step()
@@ -237,7 +239,7 @@ def main():
         "config": {"workload": w.name, "fact_rows": w.fact.n, "dim_rows": w.dim_m, "groups": groups,
                    "selected_rows": s_n, "buckets": 1 << w.log2_fanout, "filter": f"date < {w.date_hi}",
                    "topk": 100, "form": "plain (one launch chain per operator)",
-                   "partitioned": not args.no_partition,
+                   "partitioned": not args.no_partition, "probe": pl.probe,
                    "partition_items": int(os.environ.get("GQ_PARTITION_ITEMS", "16"))},
         "hbm_frac_of_peak": round(total_bytes / (ms_step * 1e6) / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_step": total_bytes,

@@ -35,6 +35,7 @@ EXPORTED = [
     "gq_ctx_create", "gq_ctx_destroy", "gq_last_error", "gq_status_word", "gq_set_timing", "gq_kernel_time",
     "gq_reset_timing", "gq_filter_workspace_bytes", "gq_filter", "gq_radix_partition_workspace_bytes",
     "gq_radix_partition", "gq_join_table_bytes", "gq_join_build_workspace_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
+    "gq_join_probe_partitioned_workspace_bytes", "gq_join_probe_partitioned",
     "gq_join_probe", "gq_groupby_workspace_bytes", "gq_groupby_agg", "gq_topk_workspace_bytes", "gq_topk",
     "gq_default_tuning", "gq_batch_workspace_bytes", "gq_batch_join_agg", "gq_batch_autotune_workspace_bytes",
     "gq_batch_autotune", "gq_server_create", "gq_server_submit", "gq_server_wait", "gq_server_stats",
@@ -138,6 +139,10 @@ def lib():
         L.gq_join_probe_workspace_bytes.argtypes = [i64]
         L.gq_join_probe.restype = st
         L.gq_join_probe.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.gq_join_probe_partitioned_workspace_bytes.restype = sz
+        L.gq_join_probe_partitioned_workspace_bytes.argtypes = [i64]
+        L.gq_join_probe_partitioned.restype = st
+        L.gq_join_probe_partitioned.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
         L.gq_groupby_workspace_bytes.restype = sz
         L.gq_groupby_workspace_bytes.argtypes = [i64, i64, i32, i32]
         L.gq_groupby_agg.restype = st
@@ -310,6 +315,23 @@ def gq_join_probe(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev
     ws = ws if ws is not None else ctx.workspace(need)
     ctx.check(lib().gq_join_probe(ctx.handle, _ptr(table), _ptr(fk), n, _ptr(n_dev), _ptr(sel), _ptr(prow),
                                   _ptr(payload), _ptr(n_out), _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return prow, payload, n_out
+
+
+def gq_join_probe_partitioned(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev=None, prow=None,
+                              payload=None, n_out=None, ws=None):
+    """Partitioned probe (per-XCD lists); returns (prow_out, payload_out, n_out),
+    the pairs of gq_join_probe in a scheduling-dependent order."""
+    if n is None:
+        n = sel.numel() if sel is not None else fk.numel()
+    prow = prow if prow is not None else torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)
+    payload = payload if payload is not None else torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)
+    n_out = n_out if n_out is not None else _i64_scalar(ctx)
+    need = lib().gq_join_probe_partitioned_workspace_bytes(n)
+    ws = ws if ws is not None else ctx.workspace(need)
+    ctx.check(lib().gq_join_probe_partitioned(ctx.handle, _ptr(table), _ptr(fk), n, _ptr(n_dev), _ptr(sel),
+                                              _ptr(prow), _ptr(payload), _ptr(n_out), _ptr(ws), ws.numel(),
+                                              _stream(ctx.device)))
     return prow, payload, n_out
 
 

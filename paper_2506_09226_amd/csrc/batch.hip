@@ -125,7 +125,8 @@ GQ_DEV int lds_group(bt_lds &T, bool active, int32_t key)
     bool done = !active;
     while (__any(!done)) {
         if (!done) {
-            const uint32_t st = atomicCAS(&T.state[s], 0u, 1u);
+            uint32_t st = __hip_atomic_load(&T.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (st == 0u) st = atomicCAS(&T.state[s], 0u, 1u);   // claim only an empty slot
             if (st == 0u) {
                 T.key[s] = key;
                 __threadfence_block();

@@ -34,6 +34,16 @@ GQ_DEV uint32_t gq_mbcnt(uint64_t mask)
 
 GQ_DEV uint64_t gq_ballot(bool p) { return __ballot(p); }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued
+// before it stay in flight (a full __syncthreads() waits for them too).  For
+// code whose threads communicate through LDS alone.
+GQ_DEV void gq_lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // A value every lane of the wave holds (read from LDS after a barrier, say),
 // moved to a scalar register so that branches on it are scalar branches.
 GQ_DEV int64_t gq_uniform(int64_t v)

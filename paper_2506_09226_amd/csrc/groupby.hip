@@ -99,16 +99,42 @@ GQ_DEV gb_row<K64, K32> load_row(const gb_args &a, int64_t j)
 }
 
 // ----------------------------------------------------------------- LDS table
+// Tables keyed by key64 use a state word (0 empty, 1 claiming, 2 published)
+// beside the key columns.  All other tables hold one 64-bit word per slot,
+// 0 = empty, else (key32 << 32) | 1, claimed and published by a single
+// compare-and-swap: one LDS access per probe and no claiming state to wait on.
 template <int SLOTS, bool K64, bool K32>
 struct lds_table {
-    uint32_t state[SLOTS];
+    uint32_t state[K64 ? SLOTS : 1];
+    uint64_t word[K64 ? 1 : SLOTS];
     uint32_t cnt[SLOTS];
-    int32_t k32[K32 ? SLOTS : 1];
+    int32_t k32[(K64 && K32) ? SLOTS : 1];
     int64_t k64[K64 ? SLOTS : 1];
     uint64_t sq[SLOTS];
     uint64_t lo[SLOTS];
     int64_t hi[SLOTS];
 };
+
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV bool lds_occupied(const lds_table<SLOTS, K64, K32> &T, int s)
+{
+    if constexpr (K64) return T.state[s] == 2u;
+    else return T.word[s] != 0ull;
+}
+
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV int32_t lds_key32(const lds_table<SLOTS, K64, K32> &T, int s)
+{
+    if constexpr (K64) return K32 ? T.k32[s] : 0;
+    else return static_cast<int32_t>(static_cast<uint32_t>(T.word[s] >> 32));
+}
+
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV int64_t lds_key64(const lds_table<SLOTS, K64, K32> &T, int s)
+{
+    if constexpr (K64) return T.k64[s];
+    else return 0;
+}
 
 template <int SLOTS>
 GQ_DEV uint32_t lds_home(uint64_t h)
@@ -121,7 +147,8 @@ template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_init(lds_table<SLOTS, K64, K32> &T)
 {
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
-        T.state[s] = 0;
+        if constexpr (K64) T.state[s] = 0;
+        else T.word[s] = 0;
         T.cnt[s] = 0;
         T.sq[s] = 0;
         T.lo[s] = 0;
@@ -137,20 +164,41 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     uint32_t s = lds_home<SLOTS>(h);
     int probes = 0, found = -1;
     bool done = !active;
+    if constexpr (!K64) {
+        const unsigned long long want = (static_cast<unsigned long long>(static_cast<uint32_t>(k32)) << 32) | 1ull;
+        while (__any(!done)) {
+            if (!done) {
+                unsigned long long *wp = reinterpret_cast<unsigned long long *>(&T.word[s]);
+                unsigned long long w = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (w == 0ull) {
+                    w = atomicCAS(wp, 0ull, want);
+                    if (w == 0ull) w = want;                  // claimed
+                }
+                if (w == want) {
+                    found = static_cast<int>(s);
+                    done = true;
+                } else if (++probes >= GB_LDS_PROBES) {
+                    done = true;
+                } else {
+                    s = (s + 1 == SLOTS) ? 0 : s + 1;
+                }
+            }
+        }
+    } else {
     while (__any(!done)) {
         if (!done) {
             // read first: most visits find a published key and need no atomic
             uint32_t st = __hip_atomic_load(&T.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (st == 0u) st = atomicCAS(&T.state[s], 0u, 1u);
             if (st == 0u) {
-                if (K64) T.k64[s] = k64;
+                T.k64[s] = k64;
                 if (K32) T.k32[s] = k32;
                 __threadfence_block();
                 atomicExch(&T.state[s], 2u);
                 found = static_cast<int>(s);
                 done = true;
             } else if (st == 2u) {
-                const bool eq = (!K64 || T.k64[s] == k64) && (!K32 || T.k32[s] == k32);
+                const bool eq = T.k64[s] == k64 && (!K32 || T.k32[s] == k32);
                 if (eq) {
                     found = static_cast<int>(s);
                     done = true;
@@ -161,6 +209,7 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
                 }
             }
         }
+    }
     }
     return found;
 }
@@ -310,9 +359,9 @@ __global__ __launch_bounds__(GB_THREADS) void gb_small_kernel(gb_args a, gtable 
     }
     __syncthreads();
     for (int s = threadIdx.x; s < GB_SMALL_SLOTS; s += GB_THREADS) {
-        const bool occ = T.state[s] == 2u;
-        const int64_t k64 = (K64 && occ) ? T.k64[s] : 0;
-        const int32_t k32 = (K32 && occ) ? T.k32[s] : 0;
+        const bool occ = lds_occupied(T, s);
+        const int64_t k64 = occ ? lds_key64(T, s) : 0;
+        const int32_t k32 = occ ? lds_key32(T, s) : 0;
         const int64_t gs = g_find<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32, status);
         if (occ && gs >= 0) {
             gq_i128 rv;
@@ -600,7 +649,7 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
     constexpr int PER = SLOTS / GB_BUCKET_THREADS;
     uint32_t mine = 0;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) mine += T.state[threadIdx.x * PER + i] == 2u ? 1u : 0u;
+    for (int i = 0; i < PER; ++i) mine += lds_occupied(T, threadIdx.x * PER + i) ? 1u : 0u;
     uint32_t total;
     uint32_t pre = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &total, scan_smem);
     if (threadIdx.x == 0)
@@ -613,9 +662,9 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int s = threadIdx.x * PER + i;
-        const bool occ = T.state[s] == 2u;
-        const int64_t k64 = (K64 && occ) ? T.k64[s] : 0;
-        const int32_t k32 = (K32 && occ) ? T.k32[s] : 0;
+        const bool occ = lds_occupied(T, s);
+        const int64_t k64 = occ ? lds_key64(T, s) : 0;
+        const int32_t k32 = occ ? lds_key32(T, s) : 0;
         uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0, lo = occ ? T.lo[s] : 0;
         int64_t hi = occ ? T.hi[s] : 0;
         if (merge) {

@@ -441,6 +441,271 @@ __global__ __launch_bounds__(JP_THREADS) void jt_probe_kernel(const void *table,
     if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
 }
 
+
+// ------------------------------------------------------------------------
+// Partitioned probe.  The probe rows are split into 8 lists by hash bits
+// 55..57, the three bits just below the top six (so a probe stream already
+// in the order of a radix partition into 64 or more buckets walks, in each
+// list, one 1/512 slice of the table at a time); the workgroups on XCD x
+// probe list x, so each XCD's L2 holds the table slice its list is reading,
+// and the table is read from HBM about once instead of one line per probe.
+//   split: each tile of 4096 probe rows counts its rows per list in LDS,
+//          reserves one run per list in a common pool (an atomic add) and
+//          records it as a chunk of that list, then writes the runs from
+//          an LDS stage: (key, probe row) pairs.
+//   probe: a persistent grid; a workgroup reads its XCD id, claims chunks of
+//          its own list (then of the others, once its list is done), probes
+//          them and appends the matches in chunk order at an atomically
+//          reserved output offset.
+// Output pairs are those of the ordered probe, in an order that depends on
+// scheduling.
+// ------------------------------------------------------------------------
+constexpr int JX_LISTS = 8;
+constexpr int JX_SHIFT = 55;
+constexpr int JX_THREADS = 256;
+constexpr int JX_ITEMS = 16;
+constexpr int JX_TILE = JX_THREADS * JX_ITEMS;          // probe rows per split tile / probe round
+constexpr int JX_CLAIM = 4;                             // chunks per claim
+
+struct jx_chunk {
+    uint32_t off, len;
+};
+
+struct jx_ws {
+    uint32_t *ctr;          // [0] pool fill, [8 + x] chunks of list x, [16 + x] chunks claimed of list x
+    jx_chunk *chunks;       // list x: chunks[x * max_chunks + i]
+    int64_t *skey;          // pool: probe keys
+    int32_t *srow;          // pool: their probe rows
+    int64_t max_chunks;     // per list: one per split tile
+};
+
+jx_ws jx_layout(gq_carver &c, int64_t n)
+{
+    jx_ws w;
+    const int64_t tiles = n > 0 ? (n + JX_TILE - 1) / JX_TILE : 1;
+    w.ctr = c.take<uint32_t>(64);
+    w.max_chunks = tiles;
+    w.chunks = c.take<jx_chunk>(static_cast<size_t>(JX_LISTS * tiles));
+    w.skey = c.take<int64_t>(static_cast<size_t>(n > 0 ? n : 1));
+    w.srow = c.take<int32_t>(static_cast<size_t>(n > 0 ? n : 1));
+    return w;
+}
+
+GQ_DEV uint32_t jx_list(int64_t key) { return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(key)) >> JX_SHIFT) & 7u; }
+
+template <bool HAS_SEL>
+__global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const int64_t *__restrict__ fk, int64_t n_bound,
+                                                              const int64_t *n_dev, const int32_t *__restrict__ sel,
+                                                              jx_ws w)
+{
+    __shared__ uint32_t cnt[JX_LISTS], start[JX_LISTS + 1], dst[JX_LISTS];
+    __shared__ int64_t stage_k[JX_TILE];
+    __shared__ int32_t stage_r[JX_TILE];
+    int64_t n = n_bound;
+    if (n_dev) {
+        const int64_t d = *n_dev;
+        n = d < n_bound ? (d > 0 ? d : 0) : n_bound;
+    }
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * JX_TILE;
+    if (base >= n) return;                               // whole block: uniform
+    if (threadIdx.x < JX_LISTS) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t k[JX_ITEMS];
+    int32_t r[JX_ITEMS];
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t e = base + c * JX_THREADS + threadIdx.x;
+        r[c] = 0;
+        if (e < n) r[c] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
+    }
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t e = base + c * JX_THREADS + threadIdx.x;
+        k[c] = e < n ? fk[r[c]] : 0;
+    }
+    uint32_t pos[JX_ITEMS];
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t e = base + c * JX_THREADS + threadIdx.x;
+        if (e < n) {
+            const uint32_t x = jx_list(k[c]);
+            pos[c] = (x << 16) | atomicAdd(&cnt[x], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int x = 0; x < JX_LISTS; ++x) {
+            start[x] = run;
+            run += cnt[x];
+            if (cnt[x]) {
+                const uint32_t off = atomicAdd(&w.ctr[0], cnt[x]);
+                const uint32_t i = atomicAdd(&w.ctr[8 + x], 1u);
+                jx_chunk ch;
+                ch.off = off;
+                ch.len = cnt[x];
+                w.chunks[static_cast<int64_t>(x) * w.max_chunks + i] = ch;
+                dst[x] = off;
+            }
+        }
+        start[JX_LISTS] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t e = base + c * JX_THREADS + threadIdx.x;
+        if (e < n) {
+            const uint32_t q = start[pos[c] >> 16] + (pos[c] & 0xffffu);
+            stage_k[q] = k[c];
+            stage_r[q] = r[c];
+        }
+    }
+    __syncthreads();
+    const uint32_t total = start[JX_LISTS];
+    for (uint32_t q = threadIdx.x; q < total; q += JX_THREADS) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int y = 1; y < JX_LISTS; ++y) x += q >= start[y] ? 1u : 0u;
+        const int64_t at = static_cast<int64_t>(dst[x]) + (q - start[x]);
+        w.skey[at] = stage_k[q];
+        w.srow[at] = stage_r[q];
+    }
+}
+
+GQ_DEV uint32_t jx_xcc_id()
+{
+    uint32_t v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 7u;
+}
+
+__global__ __launch_bounds__(JX_THREADS) void jx_probe_kernel(const void *table, jx_ws w, int32_t *__restrict__ prow_out,
+                                                              int32_t *__restrict__ pay_out, int64_t *n_out)
+{
+    __shared__ uint32_t c_off[JX_CLAIM], c_end[JX_CLAIM + 1];
+    __shared__ uint32_t s_nclaim;
+    __shared__ uint64_t bits[JX_TILE / 64];
+    __shared__ int32_t stage_row[JX_TILE];
+    __shared__ int32_t stage_pay[JX_TILE];
+    __shared__ uint32_t scan_smem[JX_THREADS / 64];
+    __shared__ unsigned long long s_out;
+    const jt_header *hdr = static_cast<const jt_header *>(table);
+    const int L = static_cast<int>(hdr->log2_slots);
+    const uint64_t mask = (1ull << L) - 1;
+    const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t list = jx_xcc_id(), tried = 0;               // used by thread 0 only
+    while (true) {
+        __syncthreads();                                  // every thread: the previous claim is done
+        if (threadIdx.x == 0) {
+            uint32_t got = 0;
+            while (tried < JX_LISTS) {
+                const uint32_t avail = w.ctr[8 + list];      // final: the split kernel has finished
+                const uint32_t i = atomicAdd(&w.ctr[16 + list], static_cast<uint32_t>(JX_CLAIM));
+                if (i < avail) {
+                    got = avail - i < static_cast<uint32_t>(JX_CLAIM) ? avail - i : static_cast<uint32_t>(JX_CLAIM);
+                    uint32_t run = 0;
+                    for (uint32_t j = 0; j < got; ++j) {
+                        const jx_chunk ch = w.chunks[static_cast<int64_t>(list) * w.max_chunks + i + j];
+                        c_off[j] = ch.off;
+                        c_end[j] = run;
+                        run += ch.len;
+                    }
+                    c_end[got] = run;
+                    break;
+                }
+                list = (list + 1) & (JX_LISTS - 1);
+                ++tried;
+            }
+            s_nclaim = got;
+        }
+        __syncthreads();
+        const uint32_t nclaim = static_cast<uint32_t>(gq_uniform(s_nclaim));
+        if (nclaim == 0) break;
+        const uint32_t total = static_cast<uint32_t>(gq_uniform(c_end[nclaim]));
+        for (uint32_t r0 = 0; r0 < total; r0 += JX_TILE) {      // rounds of up to JX_TILE entries
+            int64_t k[JX_ITEMS];
+            int32_t row[JX_ITEMS];
+            uint64_t s[JX_ITEMS];
+            int4 v[JX_ITEMS];
+#pragma unroll
+            for (int c = 0; c < JX_ITEMS; ++c) {
+                const uint32_t q = r0 + c * JX_THREADS + threadIdx.x;
+                k[c] = JT_EMPTY;
+                row[c] = 0;
+                if (q < total) {
+                    uint32_t j = 0;
+#pragma unroll
+                    for (int y = 1; y < JX_CLAIM; ++y) j += (static_cast<uint32_t>(y) < nclaim && q >= c_end[y]) ? 1u : 0u;
+                    const int64_t at = static_cast<int64_t>(c_off[j]) + (q - c_end[j]);
+                    k[c] = w.skey[at];
+                    row[c] = w.srow[at];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < JX_ITEMS; ++c) {
+                s[c] = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - L);
+                v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
+            }
+#pragma unroll
+            for (int c = 0; c < JX_ITEMS; ++c) {
+                const uint32_t q = r0 + c * JX_THREADS + threadIdx.x;
+                bool hit = false;
+                int32_t pay = 0;
+                if (q < total && k[c] != JT_EMPTY) {
+                    int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) |
+                                 static_cast<uint32_t>(v[c].x);
+                    uint64_t probes = 0;
+                    while (sk != k[c] && sk != JT_EMPTY && probes < mask) {
+                        s[c] = (s[c] + 1) & mask;
+                        v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
+                        sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
+                        ++probes;
+                    }
+                    hit = sk == k[c];
+                    pay = v[c].z;
+                }
+                const int elem = c * JX_THREADS + wave * 64 + lane;
+                stage_pay[elem] = pay;
+                stage_row[elem] = row[c];
+                const uint64_t b = gq_ballot(hit);
+                if (lane == 0) bits[c * (JX_THREADS / 64) + wave] = b;
+            }
+            __syncthreads();
+            // thread i owns round elements [16 i, 16 i + 16): gather them, then compact
+            uint32_t mine = static_cast<uint32_t>(bits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 16)) & 0xffffu;
+            int32_t my_row[JX_ITEMS], my_pay[JX_ITEMS];
+            const int elem0 = threadIdx.x * JX_ITEMS;
+#pragma unroll
+            for (int i = 0; i < JX_ITEMS; ++i) {
+                my_row[i] = stage_row[elem0 + i];
+                my_pay[i] = stage_pay[elem0 + i];
+            }
+            uint32_t hits;
+            uint32_t pos = gq_block_exclusive_scan<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &hits, scan_smem);
+            if (threadIdx.x == 0)
+                s_out = hits ? atomicAdd(reinterpret_cast<unsigned long long *>(n_out),
+                                         static_cast<unsigned long long>(hits))
+                             : 0ull;
+#pragma unroll
+            for (int i = 0; i < JX_ITEMS; ++i) {
+                if (mine & (1u << i)) {
+                    stage_row[pos] = my_row[i];
+                    stage_pay[pos] = my_pay[i];
+                    ++pos;
+                }
+            }
+            __syncthreads();
+            const int64_t goff = static_cast<int64_t>(s_out);
+            for (uint32_t i = threadIdx.x; i < hits; i += JX_THREADS) {
+                prow_out[goff + i] = stage_row[i];
+                pay_out[goff + i] = stage_pay[i];
+            }
+            __syncthreads();                              // the stage is read out before the next round
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -526,6 +791,46 @@ gq_status gq_join_probe(gq_ctx *ctx, const void *table, const int64_t *fk, int64
                          n, n_dev, sel, prow_out, payload_out, n_out_dev, w.tile_ctr, w.status);
     return gq_launch(ctx, "gq_join_probe", jt_probe_kernel<false>, dim3(grid), dim3(JP_THREADS), 0, s, table, fk, n,
                      n_dev, sel, prow_out, payload_out, n_out_dev, w.tile_ctr, w.status);
+}
+
+size_t gq_join_probe_partitioned_workspace_bytes(int64_t n)
+{
+    if (n < 0) n = 0;
+    gq_carver c(nullptr);
+    jx_layout(c, n);
+    return c.bytes();
+}
+
+gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, const int64_t *fk, int64_t n,
+                                    const int64_t *n_dev, const int32_t *sel, int32_t *prow_out,
+                                    int32_t *payload_out, int64_t *n_out_dev, void *ws, size_t ws_bytes,
+                                    gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if (n < 0 || n > GQ_MAX_ROWS)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: n=%lld", (long long)n);
+    if (!table || (!fk && n > 0) || !prow_out || !payload_out || !n_out_dev)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: NULL table, fk, output or count");
+    const size_t need = gq_join_probe_partitioned_workspace_bytes(n);
+    if (!ws || ws_bytes < need)
+        return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_join_probe_partitioned: workspace %zu < %zu bytes", ws_bytes,
+                       need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gq_carver c(ws);
+    jx_ws w = jx_layout(c, n);
+    GQ_TRY(gq_zero(ctx, w.ctr, 64, s));
+    GQ_TRY(gq_zero(ctx, n_out_dev, 2, s));
+    if (n == 0) return GQ_OK;
+    const uint32_t tiles = static_cast<uint32_t>((n + JX_TILE - 1) / JX_TILE);
+    if (sel)
+        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s, fk,
+                         n, n_dev, sel, w));
+    else
+        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s,
+                         fk, n, n_dev, sel, w));
+    const uint32_t grid = static_cast<uint32_t>(ctx->num_cus) * 4;
+    return gq_launch(ctx, "gq_join_probe_lists", jx_probe_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, w,
+                     prow_out, payload_out, n_out_dev);
 }
 
 }  // extern "C"

@@ -88,7 +88,8 @@ GQ_DEV int lds_slot(sv_lds &T, int q, bool active, int64_t key)
     bool done = !active;
     while (__any(!done)) {
         if (!done) {
-            const uint32_t st = atomicCAS(&T.state[q][s], 0u, 1u);
+            uint32_t st = __hip_atomic_load(&T.state[q][s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (st == 0u) st = atomicCAS(&T.state[q][s], 0u, 1u);   // claim only an empty slot
             if (st == 0u) {
                 T.key[q][s] = key;
                 __threadfence_block();

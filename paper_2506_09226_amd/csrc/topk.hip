@@ -9,9 +9,12 @@
 // contiguous chunk of the selection; rows whose key beats the workgroup's
 // current threshold are appended to an LDS candidate buffer; when the buffer
 // could overflow it is bitonic-sorted, cut to the best k, and the k-th key
-// becomes the new threshold.  The workgroup's best k go to a candidate array.
-// Stage 2 (one workgroup) runs the same loop over the candidates and writes
-// the final sorted answer.
+// becomes the new threshold.  The workgroup's best k go to a candidate array,
+// best first.  Row ids are loaded two steps ahead and values one step ahead,
+// and the per-step barriers order LDS only, so the loads stay in flight.
+// Stage 2 merges the candidate lists with the same buffer loop: first groups
+// of lists in parallel (one workgroup per group, each keeping its best k),
+// then one workgroup over the group results, which writes the answer.
 #include "gq_device.h"
 #include "gq_internal.h"
 
@@ -62,7 +65,7 @@ GQ_DEV void tk_sort(tk_lds &L, int size)
                     L.rk[hi] = ark;
                 }
             }
-            __syncthreads();
+            gq_lds_barrier();
         }
     }
 }
@@ -77,7 +80,7 @@ GQ_DEV void tk_compact(tk_lds &L, int k)
         L.ok[i] = 0;            // (0, 0) ranks below every real entry (rk >= 1)
         L.rk[i] = 0;
     }
-    __syncthreads();
+    gq_lds_barrier();
     tk_sort(L, size);
     if (threadIdx.x == 0) {
         if (cnt >= k) {
@@ -87,7 +90,7 @@ GQ_DEV void tk_compact(tk_lds &L, int k)
             L.has_th = 1;
         }
     }
-    __syncthreads();
+    gq_lds_barrier();
 }
 
 GQ_DEV void tk_offer(tk_lds &L, bool valid, uint64_t ok, uint32_t rk, uint64_t th_ok, uint32_t th_rk, bool has_th)
@@ -124,34 +127,31 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
         L.th_ok = 0;
         L.th_rk = 0;
     }
-    __syncthreads();
+    gq_lds_barrier();
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
-    // software pipeline: the next step's rows are loaded before this step's
-    // candidates are offered, so the loads overlap the LDS work and barriers
-    int64_t v[TK_STEP_ITEMS], vn[TK_STEP_ITEMS];
-    int32_t r[TK_STEP_ITEMS], rn[TK_STEP_ITEMS];
+    auto row_at = [&](int64_t j) -> int32_t { return j < j1 ? (sel ? sel[j] : static_cast<int32_t>(j)) : 0; };
+    // pipeline: r0/v0 = step s (offered now), r1/v1 = step s+1, r2 = step s+2
+    int32_t r0[TK_STEP_ITEMS], r1[TK_STEP_ITEMS], r2[TK_STEP_ITEMS];
+    int64_t v0[TK_STEP_ITEMS], v1[TK_STEP_ITEMS];
+#pragma unroll
+    for (int c = 0; c < TK_STEP_ITEMS; ++c) {
+        r0[c] = row_at(j0 + c * TK_THREADS + threadIdx.x);
+        r1[c] = row_at(j0 + TK_STEP + c * TK_THREADS + threadIdx.x);
+    }
 #pragma unroll
     for (int c = 0; c < TK_STEP_ITEMS; ++c) {
         const int64_t j = j0 + c * TK_THREADS + threadIdx.x;
-        r[c] = 0;
-        v[c] = 0;
-        if (j < j1) {
-            r[c] = sel ? sel[j] : static_cast<int32_t>(j);
-            v[c] = val[r[c]];
-        }
+        v0[c] = j < j1 ? val[r0[c]] : 0;
     }
     for (int64_t s = j0; s < j1; s += TK_STEP) {
 #pragma unroll
+        for (int c = 0; c < TK_STEP_ITEMS; ++c) r2[c] = row_at(s + 2 * TK_STEP + c * TK_THREADS + threadIdx.x);
+#pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
             const int64_t j = s + TK_STEP + c * TK_THREADS + threadIdx.x;
-            rn[c] = 0;
-            vn[c] = 0;
-            if (j < j1) {
-                rn[c] = sel ? sel[j] : static_cast<int32_t>(j);
-                vn[c] = val[rn[c]];
-            }
+            v1[c] = j < j1 ? val[r1[c]] : 0;
         }
         const uint64_t th_ok = L.th_ok;
         const uint32_t th_rk = L.th_rk;
@@ -159,17 +159,18 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
 #pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
             const int64_t j = s + c * TK_THREADS + threadIdx.x;
-            tk_offer(L, j < j1, tk_order(v[c], desc), 0x7fffffffu - static_cast<uint32_t>(r[c]), th_ok, th_rk,
+            tk_offer(L, j < j1, tk_order(v0[c], desc), 0x7fffffffu - static_cast<uint32_t>(r0[c]), th_ok, th_rk,
                      has_th);
         }
-        __syncthreads();
+        gq_lds_barrier();
         const uint32_t cnt_now = L.count;      // same value in every thread
-        __syncthreads();
+        gq_lds_barrier();
         if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_compact(L, k);
 #pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
-            v[c] = vn[c];
-            r[c] = rn[c];
+            r0[c] = r1[c];
+            v0[c] = v1[c];
+            r1[c] = r2[c];
         }
     }
     tk_compact(L, k);
@@ -181,11 +182,16 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
     if (threadIdx.x == 0) cand_cnt[blockIdx.x] = cnt;
 }
 
-__global__ __launch_bounds__(TK_THREADS) void topk_stage2_kernel(const uint64_t *__restrict__ cand_ok,
-                                                                 const uint32_t *__restrict__ cand_rk,
-                                                                 const uint32_t *__restrict__ cand_cnt, int nblocks,
-                                                                 int k, int desc, int64_t *__restrict__ val_out,
-                                                                 int32_t *__restrict__ rowid_out, int64_t *n_out)
+// Merge lists [blockIdx.x * per, +per) of up to k keys each (best first)
+// into the best k; the last level (out_ok == nullptr) writes the answer.
+__global__ __launch_bounds__(TK_THREADS) void topk_merge_kernel(const uint64_t *__restrict__ in_ok,
+                                                                const uint32_t *__restrict__ in_rk,
+                                                                const uint32_t *__restrict__ in_cnt, int nlists,
+                                                                int per, int k, uint64_t *__restrict__ out_ok,
+                                                                uint32_t *__restrict__ out_rk,
+                                                                uint32_t *__restrict__ out_cnt, int desc,
+                                                                int64_t *__restrict__ val_out,
+                                                                int32_t *__restrict__ rowid_out, int64_t *n_out)
 {
     __shared__ tk_lds L;
     if (threadIdx.x == 0) {
@@ -194,50 +200,63 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage2_kernel(const uint64_t 
         L.th_ok = 0;
         L.th_rk = 0;
     }
-    __syncthreads();
-    // walk the candidate array block by block, k entries per source block
-    const int64_t total = static_cast<int64_t>(nblocks) * k;
+    gq_lds_barrier();
+    const int b0 = static_cast<int>(blockIdx.x) * per;
+    const int b1 = b0 + per < nlists ? b0 + per : nlists;
+    const int64_t base = static_cast<int64_t>(b0) * k;
+    const int64_t total = b1 > b0 ? static_cast<int64_t>(b1 - b0) * k : 0;
     for (int64_t s = 0; s < total; s += TK_STEP) {
+        bool valid[TK_STEP_ITEMS];
+        uint64_t ok[TK_STEP_ITEMS];
+        uint32_t rk[TK_STEP_ITEMS];
+#pragma unroll
+        for (int c = 0; c < TK_STEP_ITEMS; ++c) {
+            const int64_t j = s + c * TK_THREADS + threadIdx.x;
+            valid[c] = false;
+            ok[c] = 0;
+            rk[c] = 0;
+            if (j < total && static_cast<uint32_t>(j % k) < in_cnt[b0 + j / k]) {
+                valid[c] = true;
+                ok[c] = in_ok[base + j];
+                rk[c] = in_rk[base + j];
+            }
+        }
         const uint64_t th_ok = L.th_ok;
         const uint32_t th_rk = L.th_rk;
         const bool has_th = L.has_th != 0;
 #pragma unroll
-        for (int c = 0; c < TK_STEP_ITEMS; ++c) {
-            const int64_t j = s + c * TK_THREADS + threadIdx.x;
-            bool valid = false;
-            uint64_t ok = 0;
-            uint32_t rk = 0;
-            if (j < total) {
-                const int64_t b = j / k, i = j % k;
-                if (i < static_cast<int64_t>(cand_cnt[b])) {
-                    valid = true;
-                    ok = cand_ok[j];
-                    rk = cand_rk[j];
-                }
-            }
-            tk_offer(L, valid, ok, rk, th_ok, th_rk, has_th);
-        }
-        __syncthreads();
+        for (int c = 0; c < TK_STEP_ITEMS; ++c) tk_offer(L, valid[c], ok[c], rk[c], th_ok, th_rk, has_th);
+        gq_lds_barrier();
         const uint32_t cnt_now = L.count;      // same value in every thread
-        __syncthreads();
+        gq_lds_barrier();
         if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_compact(L, k);
     }
     tk_compact(L, k);
     const uint32_t cnt = L.count < static_cast<uint32_t>(k) ? L.count : static_cast<uint32_t>(k);
-    for (uint32_t i = threadIdx.x; i < cnt; i += TK_THREADS) {
-        const uint64_t ok = L.ok[i];
-        const uint64_t u = desc ? ok : ~ok;
-        val_out[i] = static_cast<int64_t>(u ^ TK_SIGN);
-        rowid_out[i] = static_cast<int32_t>(0x7fffffffu - L.rk[i]);
+    if (out_ok) {
+        for (uint32_t x = threadIdx.x; x < cnt; x += TK_THREADS) {
+            out_ok[static_cast<int64_t>(blockIdx.x) * k + x] = L.ok[x];
+            out_rk[static_cast<int64_t>(blockIdx.x) * k + x] = L.rk[x];
+        }
+        if (threadIdx.x == 0) out_cnt[blockIdx.x] = cnt;
+        return;
+    }
+    for (uint32_t x = threadIdx.x; x < cnt; x += TK_THREADS) {
+        const uint64_t o = L.ok[x];
+        const uint64_t u = desc ? o : ~o;
+        val_out[x] = static_cast<int64_t>(u ^ TK_SIGN);
+        rowid_out[x] = static_cast<int32_t>(0x7fffffffu - L.rk[x]);
     }
     if (threadIdx.x == 0) *n_out = cnt;
 }
 
+constexpr int TK_MERGE_PER = 48;                      // lists per first-level merge workgroup
+
 struct tk_ws {
-    uint64_t *ok;
-    uint32_t *rk;
-    uint32_t *cnt;
-    int blocks;
+    uint64_t *ok, *ok2;
+    uint32_t *rk, *rk2;
+    uint32_t *cnt, *cnt2;
+    int blocks, groups;
     int64_t chunk;
 };
 
@@ -252,10 +271,15 @@ tk_ws tk_layout(gq_carver &c, int64_t n, int k, int num_cus)
     chunk = ((chunk + TK_STEP - 1) / TK_STEP) * TK_STEP;
     if (chunk < TK_STEP) chunk = TK_STEP;
     w.blocks = static_cast<int>(blocks);
+    w.groups = blocks > 2 * TK_MERGE_PER ? static_cast<int>((blocks + TK_MERGE_PER - 1) / TK_MERGE_PER) : 0;
     w.chunk = chunk;
     w.ok = c.take<uint64_t>(static_cast<size_t>(blocks) * k);
     w.rk = c.take<uint32_t>(static_cast<size_t>(blocks) * k);
     w.cnt = c.take<uint32_t>(static_cast<size_t>(blocks));
+    const size_t g = static_cast<size_t>(w.groups > 0 ? w.groups : 1);
+    w.ok2 = c.take<uint64_t>(g * k);
+    w.rk2 = c.take<uint32_t>(g * k);
+    w.cnt2 = c.take<uint32_t>(g);
     return w;
 }
 
@@ -292,9 +316,22 @@ gq_status gq_topk(gq_ctx *ctx, const int64_t *val, const int32_t *sel, int64_t n
     tk_ws w = tk_layout(c, n, k, tk_num_cus_for_layout());
     GQ_TRY(gq_launch(ctx, "gq_topk_local", topk_stage1_kernel, dim3(static_cast<uint32_t>(w.blocks)),
                      dim3(TK_THREADS), 0, s, val, sel, n, n_dev, k, descending ? 1 : 0, w.chunk, w.ok, w.rk, w.cnt));
-    return gq_launch(ctx, "gq_topk_merge", topk_stage2_kernel, dim3(1), dim3(TK_THREADS), 0, s,
+    const int d = descending ? 1 : 0;
+    if (w.groups > 0) {
+        GQ_TRY(gq_launch(ctx, "gq_topk_merge", topk_merge_kernel, dim3(static_cast<uint32_t>(w.groups)),
+                         dim3(TK_THREADS), 0, s, static_cast<const uint64_t *>(w.ok),
+                         static_cast<const uint32_t *>(w.rk), static_cast<const uint32_t *>(w.cnt), w.blocks,
+                         TK_MERGE_PER, k, w.ok2, w.rk2, w.cnt2, d, val_out, rowid_out, n_out_dev));
+        return gq_launch(ctx, "gq_topk_merge", topk_merge_kernel, dim3(1), dim3(TK_THREADS), 0, s,
+                         static_cast<const uint64_t *>(w.ok2), static_cast<const uint32_t *>(w.rk2),
+                         static_cast<const uint32_t *>(w.cnt2), w.groups, w.groups, k,
+                         static_cast<uint64_t *>(nullptr), static_cast<uint32_t *>(nullptr),
+                         static_cast<uint32_t *>(nullptr), d, val_out, rowid_out, n_out_dev);
+    }
+    return gq_launch(ctx, "gq_topk_merge", topk_merge_kernel, dim3(1), dim3(TK_THREADS), 0, s,
                      static_cast<const uint64_t *>(w.ok), static_cast<const uint32_t *>(w.rk),
-                     static_cast<const uint32_t *>(w.cnt), w.blocks, k, descending ? 1 : 0, val_out, rowid_out,
+                     static_cast<const uint32_t *>(w.cnt), w.blocks, w.blocks, k, static_cast<uint64_t *>(nullptr),
+                     static_cast<uint32_t *>(nullptr), static_cast<uint32_t *>(nullptr), d, val_out, rowid_out,
                      n_out_dev);
 }
 

@@ -4,6 +4,11 @@
     ->  probe(partitioned fk via the selection)  ->  group-by(dim attribute)
     ->  float64 averages  [->  top-k of price over the selection]
 
+The probe is the ordered one (gq_join_probe) or, for tables larger than the
+GPU's L2 caches together (8 x 4 MiB), the partitioned one
+(gq_join_probe_partitioned), whose pairs come in another order; the group-by
+does not depend on that order.
+
 All buffers and workspaces are allocated once, so a step allocates nothing and
 never waits for the host: every count travels on the device.
 """
@@ -12,14 +17,17 @@ from __future__ import annotations
 import torch
 
 from . import (Context, alloc_groups, gq_filter, gq_groupby_agg, gq_join_build, gq_join_probe,
-               gq_join_table_bytes, gq_radix_partition, gq_topk, lib)
+               gq_join_probe_partitioned, gq_join_table_bytes, gq_radix_partition, gq_topk, lib)
+
+L2_TOTAL_BYTES = 8 * 4 * 1024 * 1024
 
 FACT_COLS = ("date", "qty", "price", "disc")
 
 
 class PlainPipeline:
     def __init__(self, ctx: Context, fact: dict, dim: dict, date_hi: int, max_groups: int,
-                 log2_fanout: int = 6, topk: int = 100, load_factor: float = 0.5, partition: bool = True):
+                 log2_fanout: int = 6, topk: int = 100, load_factor: float = 0.5, partition: bool = True,
+                 probe: str = "auto"):
         self.ctx, self.fact, self.dim = ctx, fact, dim
         self.date_hi, self.max_groups, self.log2p = date_hi, max_groups, log2_fanout
         self.k, self.partition = topk, partition
@@ -41,7 +49,13 @@ class PlainPipeline:
         self.prow = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.pay = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
-        self.ws_probe = ctx.workspace(L.gq_join_probe_workspace_bytes(n))
+        if probe == "auto":
+            probe = "partitioned" if self.table.numel() > L2_TOTAL_BYTES else "ordered"
+        if probe not in ("ordered", "partitioned"):
+            raise ValueError(f"probe must be auto, ordered or partitioned, not {probe!r}")
+        self.probe = probe
+        self.ws_probe = ctx.workspace(L.gq_join_probe_partitioned_workspace_bytes(n) if probe == "partitioned"
+                                      else L.gq_join_probe_workspace_bytes(n))
         self.groups = alloc_groups(ctx, max_groups, False, True)
         self.ws_gb = ctx.workspace(L.gq_groupby_workspace_bytes(n, max_groups, 0, 1))
         if topk:
@@ -66,8 +80,9 @@ class PlainPipeline:
         fk, date, qty, price, disc = self.columns()
         gq_filter(ctx, date, -(1 << 31), self.date_hi, out=self.sel, n_out=self.n_sel, ws=self.ws_filter)
         gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table, ws=self.ws_build)
-        gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
-                      payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
+        probe = gq_join_probe_partitioned if self.probe == "partitioned" else gq_join_probe
+        probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow, payload=self.pay,
+              n_out=self.n_join, ws=self.ws_probe)
         gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,
                        max_groups=self.max_groups, out=self.groups, ws=self.ws_gb)
         if self.k:

@@ -211,6 +211,54 @@ def test_join_empty_sides(ctx):
     assert int(cnt.item()) == 0
 
 
+def _pairs_sorted(prow, pay, k):
+    pr, py = host(prow, k), host(pay, k)
+    o = np.argsort(pr, kind="stable")
+    return pr[o], py[o]
+
+
+@pytest.mark.parametrize("m,n,order", [(1000, 1, "random"), (60_000, 300_001, "random"),
+                                       (2_000_000, 3_000_000, "partitioned"), (2_000_000, 1_000_000, "random")])
+def test_join_probe_partitioned(ctx, m, n, order):
+    """The partitioned probe returns exactly the pairs of the ordered probe
+    (the oracle), in some order: with and without a selection, with misses,
+    with a device count, on a probe stream in radix-partition order and on a
+    random one."""
+    r = rng(m + 7 * n)
+    bkey, bpay = _dim(m, m + 3)
+    fk = np.where(r.random(n) < 0.85, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
+    fk = fk.astype(np.int64)
+    if order == "partitioned":                 # stable order by the top 6 hash bits, as after the partition
+        fk = fk[np.argsort(_fmix64_np(fk) >> np.uint64(58), kind="stable")]
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay))
+    sel = np.sort(r.choice(n, size=(2 * n) // 3, replace=False)).astype(np.int32)
+    for s in (None, sel):
+        ep, ey = oracle.join(bkey, bpay, fk, s)
+        prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=None if s is None else dev(s))
+        assert ctx.status() == gq.GQ_OK
+        k = int(cnt.item())
+        assert k == len(ep)
+        gp, gy = _pairs_sorted(prow, pay, k)
+        assert np.array_equal(gp, ep) and np.array_equal(gy, ey)       # ep is already in probe order
+    n_dev = torch.tensor([len(sel) // 2], dtype=torch.int64, device="cuda")
+    ep, ey = oracle.join(bkey, bpay, fk, sel[: len(sel) // 2])
+    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=dev(sel), n_dev=n_dev)
+    k = int(cnt.item())
+    assert k == len(ep)
+    gp, gy = _pairs_sorted(prow, pay, k)
+    assert np.array_equal(gp, ep) and np.array_equal(gy, ey)
+
+
+def test_join_probe_partitioned_empty(ctx):
+    bkey, bpay = _dim(100, 5)
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay))
+    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, torch.empty(0, dtype=torch.int64, device="cuda"))
+    assert int(cnt.item()) == 0
+    n_dev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(bkey), n_dev=n_dev)
+    assert int(cnt.item()) == 0
+
+
 # ---------------------------------------------------------------- group-by ---
 
 def _check_groups(res: gq.GroupResult, exp: dict, has64: bool, has32: bool):
@@ -425,7 +473,8 @@ def test_groupby_repeatable(ctx):
 
 # ------------------------------------------------------------------- top-k ---
 
-@pytest.mark.parametrize("n,k", [(0, 5), (3, 100), (100, 100), (50_000, 1), (1_000_003, 100), (300_000, 2048)])
+@pytest.mark.parametrize("n,k", [(0, 5), (3, 100), (100, 100), (50_000, 1), (1_000_003, 100), (300_000, 2048),
+                                 (3_000_000, 2048), (2_500_001, 7)])
 @pytest.mark.parametrize("desc", [True, False])
 def test_topk(ctx, n, k, desc):
     r = rng(n + k)
