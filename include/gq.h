@@ -200,8 +200,8 @@ gq_status gq_join_probe(gq_ctx *ctx, const void *table, const int64_t *fk,
                         int32_t *prow_out, int32_t *payload_out, int64_t *n_out_dev,
                         void *ws, size_t ws_bytes, gq_stream stream);
 
-/* Workspace for gq_join_probe_partitioned of at most n rows (about 12 bytes
- * per row plus 64 bytes per 4096 rows). */
+/* Workspace for gq_join_probe_partitioned of at most n rows (about 18 bytes
+ * per row plus 72 bytes per 4096 rows). */
 size_t gq_join_probe_partitioned_workspace_bytes(int64_t n);
 
 /* The same join as gq_join_probe, computed as a partitioned probe: the probe
@@ -212,8 +212,8 @@ size_t gq_join_probe_partitioned_workspace_bytes(int64_t n);
  * Paper: Sec. 2.2 (a local join of inputs partitioned on the key) and the
  * Related Work section (single-GPU query processing, which cites
  * partitioned radix joins).
- * Output: the same set of (prow_out, payload_out) pairs as gq_join_probe,
- * in an order that depends on scheduling; *n_out_dev the number of pairs.
+ * Output: identical to gq_join_probe's (pairs in probe order, *n_out_dev
+ * their number).
  * Arguments, errors and capacities as gq_join_probe. */
 gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, const int64_t *fk,
                                     int64_t n, const int64_t *n_dev, const int32_t *sel,

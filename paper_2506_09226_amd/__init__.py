@@ -321,7 +321,7 @@ def gq_join_probe(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev
 def gq_join_probe_partitioned(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev=None, prow=None,
                               payload=None, n_out=None, ws=None):
     """Partitioned probe (per-XCD lists); returns (prow_out, payload_out, n_out),
-    the pairs of gq_join_probe in a scheduling-dependent order."""
+    identical to gq_join_probe's output."""
     if n is None:
         n = sel.numel() if sel is not None else fk.numel()
     prow = prow if prow is not None else torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)

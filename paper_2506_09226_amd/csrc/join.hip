@@ -23,6 +23,8 @@
 // Probe: a tile of probe rows is looked up with one 16-byte load per slot
 // visited; matches become a tile bitmap (ballots) and are compacted in probe
 // order exactly like the filter: block scan + decoupled look-back + LDS stage.
+// The partitioned probe (further below) gives the same output with the table
+// reads kept in each XCD's L2.
 #include <cstdlib>
 #include <cstring>
 
@@ -449,67 +451,85 @@ __global__ __launch_bounds__(JP_THREADS) void jt_probe_kernel(const void *table,
 // list, one 1/512 slice of the table at a time); the workgroups on XCD x
 // probe list x, so each XCD's L2 holds the table slice its list is reading,
 // and the table is read from HBM about once instead of one line per probe.
-//   split: each tile of 4096 probe rows counts its rows per list in LDS,
-//          reserves one run per list in a common pool (an atomic add) and
-//          records it as a chunk of that list, then writes the runs from
-//          an LDS stage: (key, probe row) pairs.
-//   probe: a persistent grid; a workgroup reads its XCD id, claims chunks of
-//          its own list (then of the others, once its list is done), probes
-//          them and appends the matches in chunk order at an atomically
-//          reserved output offset.
-// Output pairs are those of the ordered probe, in an order that depends on
-// scheduling.
+//   split:   tile t of 4096 probe rows is regrouped by list (stable) in LDS
+//            and written to pool positions [4096 t, 4096 t + rows) as
+//            (key, index of the row inside the tile); the run of list x in
+//            tile t is chunk (x, t).  No atomics: the pool is dense over [0, n).
+//   probe:   a persistent grid of 8 G workgroups; workgroup b probes list
+//            b mod 8 (its XCD, as workgroups are dispatched round-robin over
+//            the XCDs), taking tiles in groups of 4 with stride 4 G, so the
+//            G workgroups of one XCD sweep one window of consecutive tiles;
+//            each entry's payload, or -1 for a miss, goes to its pool
+//            position.  The assignment is static: no atomics, and every
+//            chunk is probed once whatever the dispatch order.
+//   compact: per tile, the results are put back in probe order in LDS (by
+//            the stored in-tile index) and compacted exactly like the
+//            ordered probe (block scan + decoupled look-back).
+// The output is therefore identical to the ordered probe's.
 // ------------------------------------------------------------------------
 constexpr int JX_LISTS = 8;
 constexpr int JX_SHIFT = 55;
 constexpr int JX_THREADS = 256;
 constexpr int JX_ITEMS = 16;
 constexpr int JX_TILE = JX_THREADS * JX_ITEMS;          // probe rows per split tile / probe round
-constexpr int JX_CLAIM = 4;                             // chunks per claim
+constexpr int JX_GROUP = 4;                             // consecutive tiles of one list per probe step
+constexpr int JX_PITEMS = 8;                            // probe entries per thread per round
 
 struct jx_chunk {
     uint32_t off, len;
 };
 
 struct jx_ws {
-    uint32_t *ctr;          // [0] pool fill, [8 + x] chunks of list x, [16 + x] chunks claimed of list x
-    jx_chunk *chunks;       // list x: chunks[x * max_chunks + i]
+    uint32_t *ctr;          // [32] compaction tile counter
+    jx_chunk *chunks;       // chunk (x, t) at chunks[x * ntiles + t]
     int64_t *skey;          // pool: probe keys
-    int32_t *srow;          // pool: their probe rows
-    int64_t max_chunks;     // per list: one per split tile
+    uint16_t *sidx;         // pool: index of the probe row inside its tile
+    int64_t *res;           // pool: payload of the match, -1 for none
+    uint64_t *status;       // compaction look-back words, one per tile
+    int64_t ntiles;
 };
 
 jx_ws jx_layout(gq_carver &c, int64_t n)
 {
     jx_ws w;
-    const int64_t tiles = n > 0 ? (n + JX_TILE - 1) / JX_TILE : 1;
+    const int64_t rows = n > 0 ? n : 1;
+    w.ntiles = (rows + JX_TILE - 1) / JX_TILE;
     w.ctr = c.take<uint32_t>(64);
-    w.max_chunks = tiles;
-    w.chunks = c.take<jx_chunk>(static_cast<size_t>(JX_LISTS * tiles));
-    w.skey = c.take<int64_t>(static_cast<size_t>(n > 0 ? n : 1));
-    w.srow = c.take<int32_t>(static_cast<size_t>(n > 0 ? n : 1));
+    w.status = c.take<uint64_t>(static_cast<size_t>(w.ntiles));
+    w.chunks = c.take<jx_chunk>(static_cast<size_t>(JX_LISTS * w.ntiles));
+    w.skey = c.take<int64_t>(static_cast<size_t>(rows));
+    w.sidx = c.take<uint16_t>(static_cast<size_t>(rows));
+    w.res = c.take<int64_t>(static_cast<size_t>(rows));
     return w;
+}
+
+GQ_DEV int64_t jx_eff_n(int64_t bound, const int64_t *n_dev)
+{
+    if (!n_dev) return bound;
+    const int64_t d = *n_dev;
+    return d < bound ? (d > 0 ? d : 0) : bound;
 }
 
 GQ_DEV uint32_t jx_list(int64_t key) { return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(key)) >> JX_SHIFT) & 7u; }
 
+// Stable split of one tile: a row's place is its list's start in the tile,
+// plus the rows of that list in earlier (step, wave) groups, plus its rank
+// among the lanes of its wave with the same list (three ballots, one per
+// list bit).
 template <bool HAS_SEL>
 __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const int64_t *__restrict__ fk, int64_t n_bound,
                                                               const int64_t *n_dev, const int32_t *__restrict__ sel,
                                                               jx_ws w)
 {
-    __shared__ uint32_t cnt[JX_LISTS], start[JX_LISTS + 1], dst[JX_LISTS];
+    constexpr int WAVES = JX_THREADS / 64;
+    __shared__ uint32_t grp[JX_ITEMS * WAVES][JX_LISTS];   // per (step, wave): count, then exclusive prefix
+    __shared__ uint32_t start[JX_LISTS + 1];
     __shared__ int64_t stage_k[JX_TILE];
-    __shared__ int32_t stage_r[JX_TILE];
-    int64_t n = n_bound;
-    if (n_dev) {
-        const int64_t d = *n_dev;
-        n = d < n_bound ? (d > 0 ? d : 0) : n_bound;
-    }
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * JX_TILE;
-    if (base >= n) return;                               // whole block: uniform
-    if (threadIdx.x < JX_LISTS) cnt[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ uint16_t stage_i[JX_TILE];
+    const int64_t n = jx_eff_n(n_bound, n_dev);
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * JX_TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int64_t k[JX_ITEMS];
     int32_t r[JX_ITEMS];
 #pragma unroll
@@ -523,136 +543,121 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const int64_t *__r
         const int64_t e = base + c * JX_THREADS + threadIdx.x;
         k[c] = e < n ? fk[r[c]] : 0;
     }
-    uint32_t pos[JX_ITEMS];
+    uint32_t rank[JX_ITEMS];
+    uint8_t lst[JX_ITEMS];
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
         const int64_t e = base + c * JX_THREADS + threadIdx.x;
-        if (e < n) {
-            const uint32_t x = jx_list(k[c]);
-            pos[c] = (x << 16) | atomicAdd(&cnt[x], 1u);
+        const bool valid = e < n;
+        const uint32_t x = valid ? jx_list(k[c]) : 0u;
+        const uint64_t act = gq_ballot(valid);
+        const uint64_t b0 = gq_ballot(valid && (x & 1u)), b1 = gq_ballot(valid && (x & 2u)),
+                       b2 = gq_ballot(valid && (x & 4u));
+        const uint64_t peers = act & ((x & 1u) ? b0 : ~b0) & ((x & 2u) ? b1 : ~b1) & ((x & 4u) ? b2 : ~b2);
+        rank[c] = gq_mbcnt(peers);
+        lst[c] = static_cast<uint8_t>(x);
+        if (lane < JX_LISTS) {
+            const uint32_t l = static_cast<uint32_t>(lane);
+            const uint64_t ml = act & ((l & 1u) ? b0 : ~b0) & ((l & 2u) ? b1 : ~b1) & ((l & 4u) ? b2 : ~b2);
+            grp[c * WAVES + wave][l] = static_cast<uint32_t>(__popcll(ml));
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < JX_LISTS) {                     // per list: prefix over (step, wave) in row order
+        uint32_t run = 0;
+        for (int g = 0; g < JX_ITEMS * WAVES; ++g) {
+            const uint32_t c = grp[g][threadIdx.x];
+            grp[g][threadIdx.x] = run;
+            run += c;
+        }
+        start[threadIdx.x] = run;                    // list total, turned into a start below
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t run = 0;
         for (int x = 0; x < JX_LISTS; ++x) {
+            const uint32_t c = start[x];
             start[x] = run;
-            run += cnt[x];
-            if (cnt[x]) {
-                const uint32_t off = atomicAdd(&w.ctr[0], cnt[x]);
-                const uint32_t i = atomicAdd(&w.ctr[8 + x], 1u);
-                jx_chunk ch;
-                ch.off = off;
-                ch.len = cnt[x];
-                w.chunks[static_cast<int64_t>(x) * w.max_chunks + i] = ch;
-                dst[x] = off;
-            }
+            run += c;
         }
         start[JX_LISTS] = run;
     }
     __syncthreads();
+    if (threadIdx.x < JX_LISTS) {                     // every chunk is written, empty ones too
+        jx_chunk ch;
+        ch.off = static_cast<uint32_t>(base) + start[threadIdx.x];
+        ch.len = start[threadIdx.x + 1] - start[threadIdx.x];
+        w.chunks[static_cast<int64_t>(threadIdx.x) * w.ntiles + tile] = ch;
+    }
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
         const int64_t e = base + c * JX_THREADS + threadIdx.x;
         if (e < n) {
-            const uint32_t q = start[pos[c] >> 16] + (pos[c] & 0xffffu);
+            const uint32_t x = lst[c];
+            const uint32_t q = start[x] + grp[c * WAVES + wave][x] + rank[c];
             stage_k[q] = k[c];
-            stage_r[q] = r[c];
+            stage_i[q] = static_cast<uint16_t>(c * JX_THREADS + threadIdx.x);
         }
     }
     __syncthreads();
     const uint32_t total = start[JX_LISTS];
     for (uint32_t q = threadIdx.x; q < total; q += JX_THREADS) {
-        uint32_t x = 0;
-#pragma unroll
-        for (int y = 1; y < JX_LISTS; ++y) x += q >= start[y] ? 1u : 0u;
-        const int64_t at = static_cast<int64_t>(dst[x]) + (q - start[x]);
-        w.skey[at] = stage_k[q];
-        w.srow[at] = stage_r[q];
+        w.skey[base + q] = stage_k[q];
+        w.sidx[base + q] = stage_i[q];
     }
 }
 
-GQ_DEV uint32_t jx_xcc_id()
+__global__ __launch_bounds__(JX_THREADS) void jx_probe_kernel(const void *table, jx_ws w, int per_list)
 {
-    uint32_t v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    return v & 7u;
-}
-
-__global__ __launch_bounds__(JX_THREADS) void jx_probe_kernel(const void *table, jx_ws w, int32_t *__restrict__ prow_out,
-                                                              int32_t *__restrict__ pay_out, int64_t *n_out)
-{
-    __shared__ uint32_t c_off[JX_CLAIM], c_end[JX_CLAIM + 1];
-    __shared__ uint32_t s_nclaim;
-    __shared__ uint64_t bits[JX_TILE / 64];
-    __shared__ int32_t stage_row[JX_TILE];
-    __shared__ int32_t stage_pay[JX_TILE];
-    __shared__ uint32_t scan_smem[JX_THREADS / 64];
-    __shared__ unsigned long long s_out;
+    __shared__ uint32_t c_off[JX_GROUP], c_end[JX_GROUP + 1];
     const jt_header *hdr = static_cast<const jt_header *>(table);
     const int L = static_cast<int>(hdr->log2_slots);
     const uint64_t mask = (1ull << L) - 1;
     const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t list = jx_xcc_id(), tried = 0;               // used by thread 0 only
-    while (true) {
-        __syncthreads();                                  // every thread: the previous claim is done
-        if (threadIdx.x == 0) {
-            uint32_t got = 0;
-            while (tried < JX_LISTS) {
-                const uint32_t avail = w.ctr[8 + list];      // final: the split kernel has finished
-                const uint32_t i = atomicAdd(&w.ctr[16 + list], static_cast<uint32_t>(JX_CLAIM));
-                if (i < avail) {
-                    got = avail - i < static_cast<uint32_t>(JX_CLAIM) ? avail - i : static_cast<uint32_t>(JX_CLAIM);
-                    uint32_t run = 0;
-                    for (uint32_t j = 0; j < got; ++j) {
-                        const jx_chunk ch = w.chunks[static_cast<int64_t>(list) * w.max_chunks + i + j];
-                        c_off[j] = ch.off;
-                        c_end[j] = run;
-                        run += ch.len;
-                    }
-                    c_end[got] = run;
-                    break;
-                }
-                list = (list + 1) & (JX_LISTS - 1);
-                ++tried;
-            }
-            s_nclaim = got;
+    const uint32_t x = blockIdx.x % JX_LISTS;
+    const int64_t stride = static_cast<int64_t>(per_list) * JX_GROUP;
+    for (int64_t t0 = static_cast<int64_t>(blockIdx.x / JX_LISTS) * JX_GROUP; t0 < w.ntiles; t0 += stride) {
+        const uint32_t ng = static_cast<uint32_t>(w.ntiles - t0 < JX_GROUP ? w.ntiles - t0 : JX_GROUP);
+        __syncthreads();                                  // the previous group is done with c_off / c_end
+        if (threadIdx.x < ng) {
+            const jx_chunk ch = w.chunks[static_cast<int64_t>(x) * w.ntiles + t0 + threadIdx.x];
+            c_off[threadIdx.x] = ch.off;
+            c_end[threadIdx.x + 1] = ch.len;
         }
         __syncthreads();
-        const uint32_t nclaim = static_cast<uint32_t>(gq_uniform(s_nclaim));
-        if (nclaim == 0) break;
-        const uint32_t total = static_cast<uint32_t>(gq_uniform(c_end[nclaim]));
-        for (uint32_t r0 = 0; r0 < total; r0 += JX_TILE) {      // rounds of up to JX_TILE entries
-            int64_t k[JX_ITEMS];
-            int32_t row[JX_ITEMS];
-            uint64_t s[JX_ITEMS];
-            int4 v[JX_ITEMS];
+        if (threadIdx.x == 0) {
+            c_end[0] = 0;
+            for (uint32_t j = 1; j <= ng; ++j) c_end[j] += c_end[j - 1];
+        }
+        __syncthreads();
+        uint32_t e1 = c_end[1], e2 = c_end[2], e3 = c_end[3];
+        const uint32_t total = c_end[ng];
+        for (uint32_t r0 = 0; r0 < total; r0 += JX_THREADS * JX_PITEMS) {
+            int64_t k[JX_PITEMS];
+            int64_t at[JX_PITEMS];
+            uint64_t s[JX_PITEMS];
+            int4 v[JX_PITEMS];
 #pragma unroll
-            for (int c = 0; c < JX_ITEMS; ++c) {
+            for (int c = 0; c < JX_PITEMS; ++c) {
                 const uint32_t q = r0 + c * JX_THREADS + threadIdx.x;
                 k[c] = JT_EMPTY;
-                row[c] = 0;
+                at[c] = -1;
                 if (q < total) {
-                    uint32_t j = 0;
-#pragma unroll
-                    for (int y = 1; y < JX_CLAIM; ++y) j += (static_cast<uint32_t>(y) < nclaim && q >= c_end[y]) ? 1u : 0u;
-                    const int64_t at = static_cast<int64_t>(c_off[j]) + (q - c_end[j]);
-                    k[c] = w.skey[at];
-                    row[c] = w.srow[at];
+                    const uint32_t j = (q >= e1 ? 1u : 0u) + (ng > 2 && q >= e2 ? 1u : 0u) + (ng > 3 && q >= e3 ? 1u : 0u);
+                    at[c] = static_cast<int64_t>(c_off[j]) + (q - c_end[j]);
+                    k[c] = w.skey[at[c]];
                 }
             }
 #pragma unroll
-            for (int c = 0; c < JX_ITEMS; ++c) {
+            for (int c = 0; c < JX_PITEMS; ++c) {
                 s[c] = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - L);
                 v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
             }
 #pragma unroll
-            for (int c = 0; c < JX_ITEMS; ++c) {
-                const uint32_t q = r0 + c * JX_THREADS + threadIdx.x;
-                bool hit = false;
-                int32_t pay = 0;
-                if (q < total && k[c] != JT_EMPTY) {
+            for (int c = 0; c < JX_PITEMS; ++c) {
+                if (at[c] < 0) continue;
+                int64_t out = -1;
+                if (k[c] != JT_EMPTY) {
                     int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) |
                                  static_cast<uint32_t>(v[c].x);
                     uint64_t probes = 0;
@@ -662,48 +667,83 @@ __global__ __launch_bounds__(JX_THREADS) void jx_probe_kernel(const void *table,
                         sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
                         ++probes;
                     }
-                    hit = sk == k[c];
-                    pay = v[c].z;
+                    if (sk == k[c]) out = static_cast<int64_t>(static_cast<uint32_t>(v[c].z));
                 }
-                const int elem = c * JX_THREADS + wave * 64 + lane;
-                stage_pay[elem] = pay;
-                stage_row[elem] = row[c];
-                const uint64_t b = gq_ballot(hit);
-                if (lane == 0) bits[c * (JX_THREADS / 64) + wave] = b;
+                w.res[at[c]] = out;
             }
-            __syncthreads();
-            // thread i owns round elements [16 i, 16 i + 16): gather them, then compact
-            uint32_t mine = static_cast<uint32_t>(bits[threadIdx.x >> 2] >> ((threadIdx.x & 3) * 16)) & 0xffffu;
-            int32_t my_row[JX_ITEMS], my_pay[JX_ITEMS];
-            const int elem0 = threadIdx.x * JX_ITEMS;
-#pragma unroll
-            for (int i = 0; i < JX_ITEMS; ++i) {
-                my_row[i] = stage_row[elem0 + i];
-                my_pay[i] = stage_pay[elem0 + i];
-            }
-            uint32_t hits;
-            uint32_t pos = gq_block_exclusive_scan<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &hits, scan_smem);
-            if (threadIdx.x == 0)
-                s_out = hits ? atomicAdd(reinterpret_cast<unsigned long long *>(n_out),
-                                         static_cast<unsigned long long>(hits))
-                             : 0ull;
-#pragma unroll
-            for (int i = 0; i < JX_ITEMS; ++i) {
-                if (mine & (1u << i)) {
-                    stage_row[pos] = my_row[i];
-                    stage_pay[pos] = my_pay[i];
-                    ++pos;
-                }
-            }
-            __syncthreads();
-            const int64_t goff = static_cast<int64_t>(s_out);
-            for (uint32_t i = threadIdx.x; i < hits; i += JX_THREADS) {
-                prow_out[goff + i] = stage_row[i];
-                pay_out[goff + i] = stage_pay[i];
-            }
-            __syncthreads();                              // the stage is read out before the next round
         }
     }
+}
+
+// Per tile: results back in probe order (one 8-byte LDS word per entry,
+// scattered by the in-tile index), then the ordered compaction of the matches.
+template <bool HAS_SEL>
+__global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t n_bound, const int64_t *n_dev,
+                                                                const int32_t *__restrict__ sel,
+                                                                int32_t *__restrict__ prow_out,
+                                                                int32_t *__restrict__ pay_out, int64_t *n_out)
+{
+    __shared__ int64_t by_idx[JX_TILE];                   // payload or -1 in probe order; then the staged pairs
+    __shared__ uint32_t scan_smem[JX_THREADS / 64];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_goff;
+    const int64_t n = jx_eff_n(n_bound, n_dev);
+    if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctr[32], 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    const int64_t ntiles = (n + JX_TILE - 1) / JX_TILE;
+    if (static_cast<int64_t>(t) >= ntiles) {
+        if (t == 0 && threadIdx.x == 0) *n_out = 0;
+        return;
+    }
+    const int64_t base = static_cast<int64_t>(t) * JX_TILE;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t rows = n - base < JX_TILE ? n - base : JX_TILE;
+    // thread i owns probe-order elements [16 i, 16 i + 16): their rows, loaded now
+    const int elem0 = threadIdx.x * JX_ITEMS;
+    int32_t my_row[JX_ITEMS];
+#pragma unroll
+    for (int i = 0; i < JX_ITEMS; ++i) {
+        const int64_t e = base + elem0 + i;
+        my_row[i] = e < n ? (HAS_SEL ? sel[e] : static_cast<int32_t>(e)) : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t p = base + c * JX_THREADS + threadIdx.x;     // pool position
+        if (p < n) by_idx[w.sidx[p]] = w.res[p];
+    }
+    __syncthreads();
+    uint32_t mine = 0;
+    int32_t my_pay[JX_ITEMS];
+#pragma unroll
+    for (int i = 0; i < JX_ITEMS; ++i) {
+        const int64_t rv = elem0 + i < rows ? by_idx[elem0 + i] : -1;
+        mine |= rv >= 0 ? (1u << i) : 0u;
+        my_pay[i] = static_cast<int32_t>(rv);
+    }
+    uint32_t total;
+    uint32_t pos = gq_block_exclusive_scan<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+    if (wave == 0) {
+        const uint64_t g = gq_lookback(w.status, t, total);
+        if (lane == 0) s_goff = g;
+    }
+    int32_t *stage_row = reinterpret_cast<int32_t *>(by_idx);
+    int32_t *stage_pay = stage_row + JX_TILE;
+#pragma unroll
+    for (int i = 0; i < JX_ITEMS; ++i) {
+        if (mine & (1u << i)) {
+            stage_row[pos] = my_row[i];
+            stage_pay[pos] = my_pay[i];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const int64_t goff = static_cast<int64_t>(s_goff);
+    for (uint32_t i = threadIdx.x; i < total; i += JX_THREADS) {
+        prow_out[goff + i] = stage_row[i];
+        pay_out[goff + i] = stage_pay[i];
+    }
+    if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
 }
 
 }  // namespace
@@ -818,19 +858,22 @@ gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, const int64_
     hipStream_t s = static_cast<hipStream_t>(stream);
     gq_carver c(ws);
     jx_ws w = jx_layout(c, n);
-    GQ_TRY(gq_zero(ctx, w.ctr, 64, s));
-    GQ_TRY(gq_zero(ctx, n_out_dev, 2, s));
-    if (n == 0) return GQ_OK;
-    const uint32_t tiles = static_cast<uint32_t>((n + JX_TILE - 1) / JX_TILE);
+    // counters and look-back words (the prefix of the workspace up to the chunk table)
+    GQ_TRY(gq_zero(ctx, ws, static_cast<size_t>(reinterpret_cast<char *>(w.chunks) - static_cast<char *>(ws)) / 4, s));
+    const uint32_t tiles = static_cast<uint32_t>(w.ntiles);
     if (sel)
         GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s, fk,
                          n, n_dev, sel, w));
     else
         GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s,
                          fk, n, n_dev, sel, w));
-    const uint32_t grid = static_cast<uint32_t>(ctx->num_cus) * 4;
-    return gq_launch(ctx, "gq_join_probe_lists", jx_probe_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, w,
-                     prow_out, payload_out, n_out_dev);
+    const int per_list = ctx->num_cus / 2;                  // 4 workgroups per CU in all
+    GQ_TRY(gq_launch(ctx, "gq_join_probe_lists", jx_probe_kernel, dim3(static_cast<uint32_t>(per_list * JX_LISTS)),
+                     dim3(JX_THREADS), 0, s, table, w, per_list));
+    if (sel)
+        return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s,
+                         w, n, n_dev, sel, prow_out, payload_out, n_out_dev);
+    return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s, w,
+                     n, n_dev, sel, prow_out, payload_out, n_out_dev);
 }
-
 }  // extern "C"

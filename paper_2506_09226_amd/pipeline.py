@@ -4,10 +4,9 @@
     ->  probe(partitioned fk via the selection)  ->  group-by(dim attribute)
     ->  float64 averages  [->  top-k of price over the selection]
 
-The probe is the ordered one (gq_join_probe) or, for tables larger than the
-GPU's L2 caches together (8 x 4 MiB), the partitioned one
-(gq_join_probe_partitioned), whose pairs come in another order; the group-by
-does not depend on that order.
+The probe is the single-pass one (gq_join_probe, the default: faster on
+MI355X at every measured shape) or the partitioned one
+(gq_join_probe_partitioned); both give the same output.
 
 All buffers and workspaces are allocated once, so a step allocates nothing and
 never waits for the host: every count travels on the device.
@@ -18,8 +17,6 @@ import torch
 
 from . import (Context, alloc_groups, gq_filter, gq_groupby_agg, gq_join_build, gq_join_probe,
                gq_join_probe_partitioned, gq_join_table_bytes, gq_radix_partition, gq_topk, lib)
-
-L2_TOTAL_BYTES = 8 * 4 * 1024 * 1024
 
 FACT_COLS = ("date", "qty", "price", "disc")
 
@@ -50,7 +47,7 @@ class PlainPipeline:
         self.pay = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
         if probe == "auto":
-            probe = "partitioned" if self.table.numel() > L2_TOTAL_BYTES else "ordered"
+            probe = "ordered"
         if probe not in ("ordered", "partitioned"):
             raise ValueError(f"probe must be auto, ordered or partitioned, not {probe!r}")
         self.probe = probe

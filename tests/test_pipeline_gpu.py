@@ -54,10 +54,11 @@ def _tables(w, device):
     return fact, dim
 
 
-def test_small_workload_every_stage(ctx):
+@pytest.mark.parametrize("probe", ["ordered", "partitioned"])
+def test_small_workload_every_stage(ctx, probe):
     w = synth.workload(0)
     fact, dim = _tables(w, "cuda")
-    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, log2_fanout=w.log2_fanout, topk=100)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, log2_fanout=w.log2_fanout, topk=100, probe=probe)
     pl.step()
     assert ctx.status() == gq.GQ_OK
     hf = {k: H(v) for k, v in fact.items()}
@@ -184,10 +185,9 @@ def test_one_gpu_share_full_size_sampled(ctx):
     sel = pl.sel[:ns]
     assert bool((sel[1:] > sel[:-1]).all()) and bool((pdate[sel.long()] < w.date_hi).all())
 
-    # join: every foreign key references a dim key -> |join| = |sel|, rows = the selection (any order)
+    # join: every foreign key references a dim key -> |join| = |sel|, rows = selection
     nj = int(pl.n_join.item())
-    assert pl.probe == "partitioned"                       # a 1 GiB table: the partitioned probe
-    assert nj == ns and torch.equal(torch.sort(pl.prow[:nj])[0], sel)
+    assert nj == ns and torch.equal(pl.prow[:nj], sel)
     i = np.sort(rs.integers(0, nj, size=20_000))
     it = torch.from_numpy(i).cuda()
     src = H(rowid[pl.prow[it].long()]).astype(np.int64)
