@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=160)
     ap.add_argument("--serve-rows", type=int, default=1_600_000_000)
+    ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams of the served form")
     ap.add_argument("--cpu-sample", type=int, default=16_777_216)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
@@ -396,7 +397,7 @@ def bench_serve(args):
     for load in (0.8, 1.5):
         arr = synth.poisson_arrivals(len(qlist), load / t_bar, spec.seed + int(load * 10))
         subs_s, st_s = run(ser, arr)
-        srv = Server(0, fact, t1, t2, pool, streams=4, max_batch=16)
+        srv = Server(0, fact, t1, t2, pool, streams=args.serve_streams, max_batch=16)
         subs_b, st_b = run(srv, arr)
         stats = srv.stats()
         srv.close()
@@ -430,7 +431,7 @@ def bench_serve(args):
         "config": {"workload": f"served mix over {spec.n:,} resident fact rows, dims {spec.m:,} rows each; "
                                f"4 templates, selectivity U[1%,60%], Poisson arrivals",
                    "resident_bytes": resident, "pool_bytes": pool.numel(), "queries": len(qlist),
-                   "form": "served (continuous batching, shared scans, 4 streams)"},
+                   "form": f"served (continuous batching, shared scans, {args.serve_streams} streams)"},
         "p50_ms": main_load["served"]["p50_ms"],
         "p99_ms": main_load["served"]["p99_ms"],
         "serial_service_ms": round(t_bar * 1e3, 3),

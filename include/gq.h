@@ -364,8 +364,14 @@ gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
  * The paper's queries are interactive and recurring over data kept resident
  * in HBM (Sec. 4.2); the server admits queries by their memory footprint,
  * batches queries of one template that arrive while others run, and runs a
- * batch as one shared scan of the fact columns, with batches of different
- * templates overlapping on separate HIP streams (continuous batching).
+ * batch as one shared scan of the fact columns (continuous batching).
+ * Scheduling: stream 0 takes the oldest waiting query; further streams take
+ * only the short templates (FILTER_AGG, FILTER_TOPK), so long joins never
+ * share the GPU with each other.  A template's waiting queries become one
+ * shared-scan batch once there are enough of them for the shared scan to be
+ * cheaper than running them one by one (JOIN_AGG: 2, FILTER_AGG and
+ * JOIN2_AGG: 4; FILTER_TOPK: never, its plain form is cheaper); otherwise
+ * the query runs alone as the plain operator chain.
  * ------------------------------------------------------------------------ */
 
 #define GQ_QUERY_FILTER_AGG   1   /* date < date_hi, group by disc (key64)          */
@@ -388,7 +394,8 @@ typedef struct gq_server_cfg {
     gq_server_tables tables;   /* resident; must outlive the server         */
     void *pool;                /* device memory for query workspaces        */
     size_t pool_bytes;         /*   (caller-owned, 256-byte aligned)        */
-    int32_t streams;           /* batches in flight at once, 1..8           */
+    int32_t streams;           /* batches in flight at once, 1..8 (above:
+                                  stream 0 any template, others short ones) */
     int32_t max_batch;         /* queries per shared-scan batch, 1..16      */
     int32_t serial;            /* 1: each query alone with the plain
                                   operators, one at a time, arrival order   */

@@ -27,7 +27,7 @@
 namespace {
 
 constexpr int SV_THREADS = 256;
-constexpr int SV_ITEMS = 8;
+constexpr int SV_ITEMS = 16;
 constexpr int SV_TILE = SV_THREADS * SV_ITEMS;
 constexpr int SV_SLOTS = 64;                         // LDS group slots per query
 constexpr int64_t SV_EMPTY = INT64_MIN;
@@ -565,7 +565,8 @@ gq_status gq_serve_batch(gq_ctx *ctx, const gq_serve_tables &t, const gq_serve_q
     GQ_TRY(copy_outs(ctx, d_outs, q, nq, s));
     int64_t max_hi = INT32_MIN;
     for (int i = 0; i < nq; ++i) max_hi = std::max(max_hi, q[i].date_hi);
-    const int nb = std::max(1, std::min<int>(ctx->num_cus * 2, static_cast<int>((t.n + SV_TILE - 1) / SV_TILE)));
+    // three 40 KiB-LDS workgroups per CU; a persistent grid-stride loop over the rows
+    const int nb = std::max(1, std::min<int>(ctx->num_cus * 3, static_cast<int>((t.n + SV_TILE - 1) / SV_TILE)));
 
     if (kind == GQ_QUERY_FILTER_AGG || kind == GQ_QUERY_JOIN2_AGG) {
         for (int i = 0; i < nq; ++i)
