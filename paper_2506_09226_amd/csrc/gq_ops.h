@@ -21,7 +21,7 @@ gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2
 
 // In place: per-tile bucket counts cnt[t*P + b] (tile-major) become the output
 // offsets of each (tile, bucket) run; start[0..P] receives the bucket starts
-// (start[P] = total).  P <= 1024.  ws: gq_tile_offsets_workspace(ntiles, P).
+// (start[P] = total).  P <= 8192.  ws: gq_tile_offsets_workspace(ntiles, P).
 size_t gq_tile_offsets_workspace(int64_t ntiles, int P);
 gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
                           hipStream_t s, const char *name);

@@ -409,7 +409,8 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 // rows to the global table with a count of 0; a bucket whose LDS group also
 // has an entry there folds it in when it writes the group out and marks the
 // entry taken (state 3).  With no wide rows the side list stays empty.
-constexpr int GB_MAX_P = 1024;
+constexpr int GB_MAX_P = 1024;                      // buckets of the tile-staged scatter
+constexpr int GB_MAX_P_WIDE = 8192;                 // buckets of the chunked direct scatter
 constexpr int64_t GB_CUS = 256;                     // compute units of the MI355X
 constexpr int GB_BUCKET_ITEMS = 4;
 
@@ -475,24 +476,30 @@ GQ_DEV void load_key(const gb_args &a, int64_t j, int64_t &k64, int32_t &k32)
     k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
 }
 
-// LDS histogram of one tile of rows, written as the tile's row hist[t * P + b].
-template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, uint32_t *__restrict__ hist)
+// LDS histogram of one chunk of rows (chunk_rows rows from chunk * chunk_rows),
+// written as the chunk's row hist[chunk * P + b].
+template <bool K64, bool K32, int PMAX>
+__global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, int64_t chunk_rows,
+                                                             uint32_t *__restrict__ hist)
 {
     constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
-    __shared__ uint32_t h[GB_MAX_P];
+    constexpr int TILE = gb_fmt<K64, K32>::TILE;
+    __shared__ uint32_t h[PMAX];
     for (int i = threadIdx.x; i < P; i += GB_THREADS) h[i] = 0;
     __syncthreads();
     const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * gb_fmt<K64, K32>::TILE;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk_rows;
+    const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
+    for (int64_t base = c0; base < c1; base += TILE) {
 #pragma unroll 4
-    for (int c = 0; c < ITEMS; ++c) {
-        const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        if (j < n && row_pass(a, value_row(a, j))) {
-            int64_t k64;
-            int32_t k32;
-            load_key<K64, K32>(a, j, k64, k32);
-            atomicAdd(&h[gb_bucket(gb_hash(k64, k32), P)], 1u);
+        for (int c = 0; c < ITEMS; ++c) {
+            const int64_t j = base + c * GB_THREADS + threadIdx.x;
+            if (j < c1 && row_pass(a, value_row(a, j))) {
+                int64_t k64;
+                int32_t k32;
+                load_key<K64, K32>(a, j, k64, k32);
+                atomicAdd(&h[gb_bucket(gb_hash(k64, k32), P)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -599,6 +606,49 @@ __global__ __launch_bounds__(256) void gb_side_kernel(gb_args a, const uint32_t 
     }
 }
 
+// Scatter for large fan-outs (more buckets than a tile has rows): workgroup
+// c walks its chunk of rows and appends each row's record at its bucket's
+// cursor (an LDS atomic), starting from the chunk's offset gofs[c * P + b].
+// A bucket's rows from one chunk stay contiguous, so consecutive records of
+// a bucket fill whole cache lines over the walk.
+template <bool K64, bool K32>
+__global__ __launch_bounds__(GB_THREADS) void gb_scatter_wide_kernel(gb_args a, int P, int64_t chunk_rows,
+                                                                     const uint32_t *__restrict__ gofs,
+                                                                     uint64_t *__restrict__ recs,
+                                                                     uint32_t *__restrict__ side, uint32_t *side_cnt)
+{
+    constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
+    constexpr int TILE = gb_fmt<K64, K32>::TILE;
+    constexpr int W = gb_fmt<K64, K32>::WORDS;
+    __shared__ uint32_t cursor[GB_MAX_P_WIDE];
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) cursor[b] = gofs[static_cast<int64_t>(blockIdx.x) * P + b];
+    __syncthreads();
+    const int64_t n = eff_n(a.n_bound, a.n_dev);
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk_rows;
+    const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
+    for (int64_t base = c0; base < c1; base += TILE) {
+#pragma unroll 4
+        for (int c = 0; c < ITEMS; ++c) {
+            const int64_t j = base + c * GB_THREADS + threadIdx.x;
+            if (j >= c1) continue;
+            const int64_t v = value_row(a, j);
+            if (!row_pass(a, v)) continue;
+            const int64_t k64 = K64 ? a.key64[a.key64_by_rowid ? v : j] : 0;
+            const int32_t k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
+            const int64_t qty = a.qty[v];
+            const gq_i128 rev = gq_revenue(a.price[v], a.rev_scale, a.disc[v]);
+            const bool nar = is_narrow(qty, rev);
+            if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
+            uint64_t w[W];
+            make_words<K64, K32>(w, k64, k32, nar ? static_cast<int32_t>(qty) : 0,
+                                 nar ? static_cast<int64_t>(rev.lo) : 0);
+            const uint32_t pos = atomicAdd(&cursor[gb_bucket(gb_hash(k64, k32), P)], 1u);
+#pragma unroll
+            for (int x = 0; x < W; ++x) recs[static_cast<int64_t>(pos) * W + x] = w[x];
+        }
+    }
+}
+
 template <bool K64, bool K32>
 struct bucket_slots {
     static constexpr int value = K64 ? 3072 : 4096;
@@ -696,7 +746,9 @@ uint64_t next_pow2(uint64_t x)
 struct gb_plan {
     bool small;
     int P;                  // buckets of the large path
-    int64_t ntiles;         // hist/scatter tiles
+    bool wide;              // P > GB_MAX_P: chunked hist and direct scatter
+    int64_t ntiles;         // hist/scatter workgroups (tiles, or chunks when wide)
+    int64_t chunk_rows;     // rows per hist/scatter workgroup
     int words;              // 8-byte words per partitioned record
     uint64_t gslots;
 };
@@ -708,6 +760,7 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
     pl.small = max_groups <= GB_SMALL_GROUPS;
     pl.gslots = next_pow2(static_cast<uint64_t>(max_groups > 32 ? 2 * max_groups : 64));
     const int64_t tile = static_cast<int64_t>(GB_THREADS) * (k64 ? 8 : 16);
+    pl.chunk_rows = tile;
     pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
     pl.words = k64 ? 3 : 2;
     if (!pl.small) {
@@ -717,7 +770,14 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
         // one 1024-thread workgroup per bucket and one per CU at a time: a
         // whole number of rounds over the CUs leaves no idle tail
         if (P > GB_CUS) P = (P + GB_CUS - 1) / GB_CUS * GB_CUS;
-        pl.P = static_cast<int>(std::min<int64_t>(std::max<int64_t>(P, 2), GB_MAX_P));
+        pl.P = static_cast<int>(std::min<int64_t>(std::max<int64_t>(P, 2), GB_MAX_P_WIDE));
+        pl.wide = pl.P > GB_MAX_P;
+        if (pl.wide) {                      // 2048 chunks of whole tiles
+            const int64_t tiles = pl.ntiles;
+            const int64_t per = (tiles + 2047) / 2048;
+            pl.chunk_rows = per * tile;
+            pl.ntiles = n > 0 ? (n + pl.chunk_rows - 1) / pl.chunk_rows : 1;
+        }
     }
     return pl;
 }
@@ -775,11 +835,20 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                          w.g, out, ctx->status_dev);
     }
     const uint32_t grid = static_cast<uint32_t>(pl.ntiles);
-    GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a, pl.P,
-                     w.hist));
+    if (pl.wide)
+        GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P_WIDE>, dim3(grid), dim3(GB_THREADS),
+                         0, s, a, pl.P, pl.chunk_rows, w.hist));
+    else
+        GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P>, dim3(grid), dim3(GB_THREADS), 0,
+                         s, a, pl.P, pl.chunk_rows, w.hist));
     GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, pl.P, w.start, w.scan_ws, s, "gq_groupby_scan"));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s, a,
-                     pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt));
+    if (pl.wide)
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_wide_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0,
+                         s, a, pl.P, pl.chunk_rows, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
+                         w.side_cnt));
+    else
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s,
+                         a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt));
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));

@@ -82,7 +82,8 @@ namespace {
 
 constexpr int TO_CHUNK = 256;
 constexpr int TO_THREADS = 256;
-constexpr int TO_MAX_P = 1024;
+constexpr int TO_MAX_P = 8192;
+constexpr int TO_START_THREADS = 1024;
 
 __global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
                                                                   int P, uint32_t *__restrict__ csum)
@@ -113,14 +114,24 @@ __global__ __launch_bounds__(TO_THREADS) void to_chunk_scan_kernel(uint32_t *__r
     total[b] = run;
 }
 
-__global__ __launch_bounds__(TO_MAX_P) void to_bucket_start_kernel(const uint32_t *__restrict__ total, int P,
-                                                                   uint32_t *__restrict__ start)
+// Exclusive scan of the P bucket totals (one workgroup; each thread owns
+// P / 1024 consecutive buckets).
+__global__ __launch_bounds__(TO_START_THREADS) void to_bucket_start_kernel(const uint32_t *__restrict__ total, int P,
+                                                                           uint32_t *__restrict__ start)
 {
-    __shared__ uint32_t smem[TO_MAX_P / 64];
-    const uint32_t v = threadIdx.x < static_cast<unsigned>(P) ? total[threadIdx.x] : 0u;
+    __shared__ uint32_t smem[TO_START_THREADS / 64];
+    const int per = (P + TO_START_THREADS - 1) / TO_START_THREADS;
+    const int b0 = threadIdx.x * per;
+    uint32_t v = 0;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < P) v += total[b0 + i];
     uint32_t all;
-    const uint32_t ex = gq_block_exclusive_scan<TO_MAX_P>(v, &all, smem);
-    if (threadIdx.x < static_cast<unsigned>(P)) start[threadIdx.x] = ex;
+    uint32_t run = gq_block_exclusive_scan<TO_START_THREADS>(v, &all, smem);
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < P) {
+            start[b0 + i] = run;
+            run += total[b0 + i];
+        }
     if (threadIdx.x == 0) start[P] = all;
 }
 
@@ -166,7 +177,7 @@ gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uin
     GQ_TRY(gq_launch(ctx, name, to_chunk_sum_kernel, grid2, dim3(TO_THREADS), 0, s,
                      static_cast<const uint32_t *>(cnt), ntiles, P, csum));
     GQ_TRY(gq_launch(ctx, name, to_chunk_scan_kernel, grid1, dim3(TO_THREADS), 0, s, csum, nchunks, P, total));
-    GQ_TRY(gq_launch(ctx, name, to_bucket_start_kernel, dim3(1), dim3(TO_MAX_P), 0, s,
+    GQ_TRY(gq_launch(ctx, name, to_bucket_start_kernel, dim3(1), dim3(TO_START_THREADS), 0, s,
                      static_cast<const uint32_t *>(total), P, start));
     return gq_launch(ctx, name, to_final_kernel, grid2, dim3(TO_THREADS), 0, s, cnt, ntiles, P,
                      static_cast<const uint32_t *>(csum), static_cast<const uint32_t *>(start));

@@ -448,6 +448,35 @@ def test_groupby_large_path_wide_rows(ctx, composite, overflow):
     _check_groups(res, exp, composite, True)
 
 
+@pytest.mark.parametrize("composite", [False, True])
+def test_groupby_wide_fanout(ctx, composite):
+    """Millions of groups: more buckets than the tile-staged scatter takes
+    (chunked histogram, direct scatter), with some rows too wide for a
+    narrow record; exact against the oracle."""
+    r = rng(77 + int(composite))
+    n = nv = 6_000_000
+    groups = 2_600_000
+    keys = np.unique(r.integers(0, 1 << 31, size=groups)).astype(np.int32)
+    key32 = keys[r.integers(0, len(keys), size=n)]
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    wide = np.nonzero(r.random(nv) < 0.001)[0]
+    qty[wide] = 1 << 40
+    if composite:
+        key64 = (key32.astype(np.int64) * 1_000_003) ^ (1 << 50)
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                                key32=dev(key32), max_groups=3_000_000)
+    else:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                                max_groups=3_000_000)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, composite, True)
+
+
 def test_groupby_repeatable(ctx):
     """Integer results are identical run to run (no scheduling dependence)."""
     n = 500_000

@@ -143,6 +143,48 @@ def test_skewed_workload_reduced(ctx):
     assert np.array_equal(H(pl.tk_val), ev) and np.array_equal(H(pl.tk_row), er)
 
 
+def test_skewed_workload_full_size_sampled(ctx):
+    """100M fact rows with Zipf(1.0) foreign keys over a 10M-row dimension:
+    the composite-key group-by over all rows (about ten million groups) and
+    the 5% filter -> join -> group-by pipeline, checked by totals, the exact
+    distinct count and sampled groups recomputed by the oracle."""
+    w = synth.workload(2)
+    fact, dim = _tables(w, "cuda")
+    n = w.fact.n
+    res = gq.gq_groupby_agg(ctx, fact["qty"], fact["price"], fact["disc"], key64=fact["fk"], key32=fact["g32"],
+                            max_groups=16_000_000)
+    torch.cuda.synchronize()
+    assert ctx.status() == gq.GQ_OK
+    ng = int(res.n_groups.item())
+    fk, g32 = fact["fk"], fact["g32"]
+    distinct = sum(int(torch.unique(fk[g32 == g]).numel()) for g in (0, 1))
+    assert ng == distinct and 8_000_000 < ng < 12_000_000
+    cnt = res.count[:ng]
+    assert int(cnt.sum().item()) == n
+    assert int(res.sum_qty[:ng].sum().item()) == int(fact["qty"].sum().item())
+    assert bool((res.sum_rev_hi[:ng] == 0).all())
+    rev_total = int((fact["price"] * (100 - fact["disc"])).sum().item())
+    assert int(res.sum_rev_lo[:ng].sum().item()) == rev_total
+    rs = np.random.default_rng(7)
+    big = int(torch.argmax(cnt).item())
+    for gi in [big] + list(rs.choice(ng, size=3, replace=False)):
+        k64, k32 = int(res.key64[gi].item()), int(res.key32[gi].item())
+        rows = torch.nonzero((fk == k64) & (g32 == k32)).flatten()
+        e = oracle.groupby(len(rows), H(fact["qty"][rows]), H(fact["price"][rows]), H(fact["disc"][rows]))
+        for f in ("count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
+            assert int(getattr(res, f)[gi].item()) == int(e[f][0]), f
+        np.testing.assert_allclose(res.avg_rev[gi].item(), e["avg_rev"][0], rtol=1e-12, atol=0)
+    # the filtered pipeline: 5% of rows, all of them match a dimension key
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, partition=False, topk=100)
+    pl.step()
+    torch.cuda.synchronize()
+    assert ctx.status() == gq.GQ_OK
+    ns, nj = int(pl.n_sel.item()), int(pl.n_join.item())
+    assert ns == int((fact["date"] < w.date_hi).sum().item()) and nj == ns
+    g = pl.groups.host()
+    assert int(g["count"].sum()) == nj
+
+
 def test_one_gpu_share_full_size_sampled(ctx):
     """200M fact rows, 25M dim rows, 64 buckets, ~1.5M groups: the benchmark's
     launch configuration, checked on sampled outputs and invariants."""
