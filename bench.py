@@ -128,7 +128,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=160)
     ap.add_argument("--serve-rows", type=int, default=1_600_000_000)
     ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams of the served form")
-    ap.add_argument("--cpu-sample", type=int, default=16_777_216)
+    ap.add_argument("--cpu-sample", type=int, default=33_554_432)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--probe", default="auto", choices=["auto", "ordered", "partitioned"],
