@@ -9,7 +9,8 @@ size_t gq_scan_u32_workspace(int64_t n);
 gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStream_t s, const char *name);
 
 // Stable partition of n rows by the log2p (0..8) bits of fmix64(key) that
-// start at bit `shift` (no row ids).  ws: gq_partition_bits_workspace(n, log2p).
+// start at bit `shift` (no row ids), with tiles of 256 * items rows (items 8,
+// 16 or 32; 0 = the operator's default).  ws: gq_partition_bits_workspace(n, log2p).
 size_t gq_partition_bits_workspace(int64_t n, int log2p);
 // Kernel names of one use of the partition (for per-kernel timing).
 struct gq_part_names {
@@ -17,7 +18,7 @@ struct gq_part_names {
 };
 gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, int ncols,
                             void *const *cols, const int32_t *col_bytes, int64_t *key_out, void *const *cols_out,
-                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &names);
+                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &names, int items);
 
 // In place: per-tile bucket counts cnt[t*P + b] (tile-major) become the output
 // offsets of each (tile, bucket) run; start[0..P] receives the bucket starts

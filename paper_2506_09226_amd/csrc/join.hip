@@ -301,15 +301,15 @@ gq_status region_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, 
     if (g <= 8) {
         void *in[1] = {const_cast<int32_t *>(payload)};
         void *out[1] = {w.p2};
-        GQ_TRY(gq_partition_bits(ctx, key, m, g, 64 - g, 1, in, &pbytes, w.k2, out, w.offsets, w.part_ws, s, nm));
+        GQ_TRY(gq_partition_bits(ctx, key, m, g, 64 - g, 1, in, &pbytes, w.k2, out, w.offsets, w.part_ws, s, nm, 8));
     } else {                                        // LSD: low digit first, both passes stable
         const int d1 = g / 2, d2 = g - d1;
         void *in1[1] = {const_cast<int32_t *>(payload)};
         void *out1[1] = {w.p1};
-        GQ_TRY(gq_partition_bits(ctx, key, m, d1, 64 - g, 1, in1, &pbytes, w.k1, out1, w.offsets, w.part_ws, s, nm));
+        GQ_TRY(gq_partition_bits(ctx, key, m, d1, 64 - g, 1, in1, &pbytes, w.k1, out1, w.offsets, w.part_ws, s, nm, 8));
         void *in2[1] = {w.p1};
         void *out2[1] = {w.p2};
-        GQ_TRY(gq_partition_bits(ctx, w.k1, m, d2, 64 - d2, 1, in2, &pbytes, w.k2, out2, w.offsets, w.part_ws, s, nm));
+        GQ_TRY(gq_partition_bits(ctx, w.k1, m, d2, 64 - d2, 1, in2, &pbytes, w.k2, out2, w.offsets, w.part_ws, s, nm, 8));
     }
     uint64_t bb = (static_cast<uint64_t>(m) + 256) / 256;
     if (bb > 8192) bb = 8192;

@@ -159,30 +159,47 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
     const int64_t rem = n - base;
     const uint32_t count = static_cast<uint32_t>(rem < TILE ? rem : TILE);
 
-    // column 0 = key (in registers), 1..ncols = payload columns, last = row id
+    // column 0 = key (in registers), 1..ncols = payload columns, last = row id.
+    // The next column's loads are issued before the current column is written
+    // out, and the barriers order LDS only, so loads and stores of neighbouring
+    // columns overlap.
     const int ncol_total = 1 + cols.n + (rowid_out ? 1 : 0);
+    auto load_col = [&](int ci, uint64_t *v) {
+        const bool is_key = ci == 0;
+        const bool is_rowid = ci == 1 + cols.n;
+        const int width = is_key ? 8 : (is_rowid ? 4 : cols.bytes[ci - 1]);
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            const int64_t e = row0 + c * 64;
+            uint64_t x = 0;
+            if (e < n) {
+                if (is_key) x = static_cast<uint64_t>(k[c]);
+                else if (is_rowid) x = static_cast<uint32_t>(e);
+                else if (width == 8) x = static_cast<const uint64_t *>(cols.in[ci - 1])[e];
+                else x = static_cast<const uint32_t *>(cols.in[ci - 1])[e];
+            }
+            v[c] = x;
+        }
+    };
+    uint64_t cur[ITEMS], nxt[ITEMS];
+    load_col(0, cur);
     for (int ci = 0; ci < ncol_total; ++ci) {
         const bool is_key = ci == 0;
         const bool is_rowid = ci == 1 + cols.n;
         const int width = is_key ? 8 : (is_rowid ? 4 : cols.bytes[ci - 1]);
-        __syncthreads();                              // stage free (and lbucket ready)
+        gq_lds_barrier();                             // stage free (and lbucket ready)
         if (width == 8) {
-            const int64_t *src = is_key ? nullptr : static_cast<const int64_t *>(cols.in[ci - 1]);
 #pragma unroll
-            for (int c = 0; c < ITEMS; ++c) {
-                const int64_t e = row0 + c * 64;
-                if (e < n) stage[pos[c]] = static_cast<uint64_t>(is_key ? k[c] : src[e]);
-            }
+            for (int c = 0; c < ITEMS; ++c)
+                if (row0 + c * 64 < n) stage[pos[c]] = cur[c];
         } else {
             uint32_t *st32 = reinterpret_cast<uint32_t *>(stage);
-            const int32_t *src = is_rowid ? nullptr : static_cast<const int32_t *>(cols.in[ci - 1]);
 #pragma unroll
-            for (int c = 0; c < ITEMS; ++c) {
-                const int64_t e = row0 + c * 64;
-                if (e < n) st32[pos[c]] = static_cast<uint32_t>(is_rowid ? static_cast<int32_t>(e) : src[e]);
-            }
+            for (int c = 0; c < ITEMS; ++c)
+                if (row0 + c * 64 < n) st32[pos[c]] = static_cast<uint32_t>(cur[c]);
         }
-        __syncthreads();
+        if (ci + 1 < ncol_total) load_col(ci + 1, nxt);
+        gq_lds_barrier();
         if (width == 8) {
             uint64_t *dst = is_key ? reinterpret_cast<uint64_t *>(key_out) : static_cast<uint64_t *>(cols.out[ci - 1]);
             for (uint32_t q = threadIdx.x; q < count; q += PT_THREADS) {
@@ -197,6 +214,8 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
                 dst[gstart[b] + (q - lstart[b])] = st32[q];
             }
         }
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) cur[c] = nxt[c];
     }
 }
 
@@ -255,9 +274,9 @@ gq_status run_partition_items(gq_ctx *ctx, const int64_t *key, int64_t n, int sh
 template <int LOG2P>
 gq_status run_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int shift, const part_cols &cols,
                         int64_t *key_out, int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s,
-                        const gq_part_names &nm)
+                        const gq_part_names &nm, int items)
 {
-    switch (part_items()) {
+    switch (items > 0 ? items : part_items()) {
     case 8: return run_partition_items<LOG2P, 8>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
     case 32: return run_partition_items<LOG2P, 32>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
     default: return run_partition_items<LOG2P, 16>(ctx, key, n, shift, cols, key_out, rowid_out, offsets, w, s, nm);
@@ -266,18 +285,18 @@ gq_status run_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int shift, c
 
 gq_status dispatch_partition(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, const part_cols &pc,
                              int64_t *key_out, int32_t *rowid_out, int64_t *offsets, part_ws w, hipStream_t s,
-                             const gq_part_names &nm)
+                             const gq_part_names &nm, int items = 0)
 {
     switch (log2p) {
-    case 0: return run_partition<0>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 1: return run_partition<1>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 2: return run_partition<2>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 3: return run_partition<3>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 4: return run_partition<4>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 5: return run_partition<5>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 6: return run_partition<6>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    case 7: return run_partition<7>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
-    default: return run_partition<8>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm);
+    case 0: return run_partition<0>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 1: return run_partition<1>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 2: return run_partition<2>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 3: return run_partition<3>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 4: return run_partition<4>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 5: return run_partition<5>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 6: return run_partition<6>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    case 7: return run_partition<7>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
+    default: return run_partition<8>(ctx, key, n, shift, pc, key_out, rowid_out, offsets, w, s, nm, items);
     }
 }
 
@@ -292,7 +311,7 @@ size_t gq_partition_bits_workspace(int64_t n, int log2p)
 
 gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2p, int shift, int ncols,
                             void *const *cols, const int32_t *col_bytes, int64_t *key_out, void *const *cols_out,
-                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &nm)
+                            int64_t *offsets, void *ws, hipStream_t s, const gq_part_names &nm, int items)
 {
     part_cols pc{};
     pc.n = ncols;
@@ -303,7 +322,7 @@ gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2
     }
     gq_carver c(ws);
     part_ws w = part_layout(c, n, log2p);
-    return dispatch_partition(ctx, key, n, log2p, shift, pc, key_out, nullptr, offsets, w, s, nm);
+    return dispatch_partition(ctx, key, n, log2p, shift, pc, key_out, nullptr, offsets, w, s, nm, items);
 }
 
 extern "C" {
