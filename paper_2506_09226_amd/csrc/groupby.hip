@@ -417,7 +417,7 @@ constexpr int GB_BUCKET_ITEMS = 4;
 template <bool K64, bool K32>
 struct gb_fmt {
     static constexpr int WORDS = K64 ? 3 : 2;
-    static constexpr int ITEMS = K64 ? 8 : 16;           // rows per thread of a hist/scatter tile
+    static constexpr int ITEMS = 8;                      // rows per thread of a hist/scatter tile
     static constexpr int TILE = GB_THREADS * ITEMS;
 };
 
@@ -759,7 +759,7 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
     gb_plan pl{};
     pl.small = max_groups <= GB_SMALL_GROUPS;
     pl.gslots = next_pow2(static_cast<uint64_t>(max_groups > 32 ? 2 * max_groups : 64));
-    const int64_t tile = static_cast<int64_t>(GB_THREADS) * (k64 ? 8 : 16);
+    const int64_t tile = static_cast<int64_t>(GB_THREADS) * 8;        // gb_fmt<>::TILE
     pl.chunk_rows = tile;
     pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
     pl.words = k64 ? 3 : 2;
