@@ -25,6 +25,7 @@
 // order exactly like the filter: block scan + decoupled look-back + LDS stage.
 // The partitioned probe (further below) gives the same output with the table
 // reads kept in each XCD's L2.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 
@@ -142,53 +143,17 @@ __global__ __launch_bounds__(256) void jt_region_bounds_kernel(const int64_t *__
     }
 }
 
+// A persistent grid walks the regions; the barriers between a region's phases
+// order LDS only, so one region's table stores drain while the next region's
+// keys load.
 __global__ __launch_bounds__(256) void jt_region_kernel(void *table, int L, const int64_t *__restrict__ keys,
                                                         const int32_t *__restrict__ pay,
-                                                        const int64_t *__restrict__ roff,
+                                                        const int64_t *__restrict__ roff, int64_t nregions,
                                                         int64_t *__restrict__ ovf_key, int32_t *__restrict__ ovf_pay,
                                                         uint32_t *ovf_cnt, int64_t ovf_cap, uint32_t *status)
 {
     __shared__ unsigned long long sk[JR_SLOTS];
     __shared__ int32_t sp[JR_SLOTS];
-    const uint64_t region = blockIdx.x;
-    for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
-        sk[j] = static_cast<unsigned long long>(JT_EMPTY);
-        sp[j] = 0;
-    }
-    __syncthreads();
-    const int64_t r0 = roff[region], r1 = roff[region + 1];
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const int64_t k = keys[i];
-        const int32_t p = pay[i];
-        if (k == JT_EMPTY) {
-            gq_raise(status, GQ_ERR_INVALID_KEY);
-            continue;
-        }
-        uint32_t loc = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k)) >> (64 - L)) & (JR_SLOTS - 1);
-        while (true) {
-            const unsigned long long prev =
-                atomicCAS(&sk[loc], static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
-            if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
-                sp[loc] = p;
-                break;
-            }
-            if (prev == static_cast<unsigned long long>(k)) {
-                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
-                break;
-            }
-            if (++loc == JR_SLOTS) {                 // continue in the next region, later
-                const uint32_t idx = atomicAdd(ovf_cnt, 1u);
-                if (idx < ovf_cap) {
-                    ovf_key[idx] = k;
-                    ovf_pay[idx] = p;
-                } else {
-                    gq_raise(status, GQ_ERR_CAPACITY);
-                }
-                break;
-            }
-        }
-    }
-    __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         jt_header *h = static_cast<jt_header *>(table);
         h->magic = JT_MAGIC;
@@ -196,13 +161,55 @@ __global__ __launch_bounds__(256) void jt_region_kernel(void *table, int L, cons
         h->unused = 0;
         h->slots = 1ull << L;
     }
-    jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER) + (region << JR_BITS);
-    for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
-        jt_slot e;
-        e.key = static_cast<int64_t>(sk[j]);
-        e.payload = sp[j];
-        e.unused = 0;
-        slots[j] = e;
+    for (int64_t region = blockIdx.x; region < nregions; region += gridDim.x) {
+        gq_lds_barrier();                             // the previous region is read out of LDS
+        for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+            sk[j] = static_cast<unsigned long long>(JT_EMPTY);
+            sp[j] = 0;
+        }
+        gq_lds_barrier();
+        const int64_t r0 = roff[region], r1 = roff[region + 1];
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            const int64_t k = keys[i];
+            const int32_t p = pay[i];
+            if (k == JT_EMPTY) {
+                gq_raise(status, GQ_ERR_INVALID_KEY);
+                continue;
+            }
+            uint32_t loc = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k)) >> (64 - L)) & (JR_SLOTS - 1);
+            while (true) {
+                const unsigned long long prev =
+                    atomicCAS(&sk[loc], static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
+                if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
+                    sp[loc] = p;
+                    break;
+                }
+                if (prev == static_cast<unsigned long long>(k)) {
+                    gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                    break;
+                }
+                if (++loc == JR_SLOTS) {                 // continue in the next region, later
+                    const uint32_t idx = atomicAdd(ovf_cnt, 1u);
+                    if (idx < ovf_cap) {
+                        ovf_key[idx] = k;
+                        ovf_pay[idx] = p;
+                    } else {
+                        gq_raise(status, GQ_ERR_CAPACITY);
+                    }
+                    break;
+                }
+            }
+        }
+        gq_lds_barrier();
+        jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER) +
+                         (static_cast<uint64_t>(region) << JR_BITS);
+        for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+            jt_slot e;
+            e.key = static_cast<int64_t>(sk[j]);
+            e.payload = sp[j];
+            e.unused = 0;
+            slots[j] = e;
+        }
     }
 }
 
@@ -315,9 +322,11 @@ gq_status region_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, 
     if (bb > 8192) bb = 8192;
     GQ_TRY(gq_launch(ctx, "gq_join_build_bounds", jt_region_bounds_kernel, dim3(static_cast<uint32_t>(bb)), dim3(256),
                      0, s, static_cast<const int64_t *>(w.k2), m, g, w.roff));
-    GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(1u << g), dim3(256), 0, s, table, L,
+    const int64_t nregions = int64_t(1) << g;
+    const uint32_t rgrid = static_cast<uint32_t>(std::min<int64_t>(nregions, int64_t(ctx->num_cus) * 3));
+    GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(rgrid), dim3(256), 0, s, table, L,
                      static_cast<const int64_t *>(w.k2), static_cast<const int32_t *>(w.p2),
-                     static_cast<const int64_t *>(w.roff), w.ovf_key, w.ovf_pay, w.ovf_cnt, w.ovf_cap,
+                     static_cast<const int64_t *>(w.roff), nregions, w.ovf_key, w.ovf_pay, w.ovf_cnt, w.ovf_cap,
                      ctx->status_dev));
     return gq_launch(ctx, "gq_join_build_overflow", jt_overflow_kernel, dim3(64), dim3(256), 0, s, table, L,
                      static_cast<const int64_t *>(w.ovf_key), static_cast<const int32_t *>(w.ovf_pay),
