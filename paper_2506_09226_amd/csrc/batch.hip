@@ -250,41 +250,73 @@ __device__ void item_init(const bt_inst &I, int64_t tile, int init_tile)
     }
 }
 
+// Build tile: keys in groups of 8 per thread, so their first
+// compare-and-swap attempts (one slot each, usually a free one at load
+// factor <= 0.9) are in flight together; collisions then walk on one by one.
+constexpr int BT_BUILD_ITEMS = 8;
+
 __device__ void item_build(const bt_inst &I, int64_t tile, int build_tile, uint32_t *status)
 {
     const int L = I.log2_slots;
     const uint64_t mask = (1ull << L) - 1;
     const int64_t a = tile * build_tile, b = (a + build_tile < I.m) ? a + build_tile : I.m;
-    for (int64_t i = a + threadIdx.x; i < b; i += BT_THREADS) {
-        const int64_t k = I.dim_key[i];
-        if (k == BT_EMPTY) {
-            gq_raise(status, GQ_ERR_INVALID_KEY);
-            continue;
+    for (int64_t i0 = a; i0 < b; i0 += BT_THREADS * BT_BUILD_ITEMS) {
+        int64_t k[BT_BUILD_ITEMS];
+        int32_t pay[BT_BUILD_ITEMS];
+        bool valid[BT_BUILD_ITEMS];
+#pragma unroll
+        for (int c = 0; c < BT_BUILD_ITEMS; ++c) {
+            const int64_t i = i0 + c * BT_THREADS + threadIdx.x;
+            valid[c] = i < b;
+            k[c] = valid[c] ? I.dim_key[i] : 0;
+            pay[c] = valid[c] ? I.dim_attr[i] : 0;
         }
-        uint64_t s = key_hash(k) >> (64 - L);
-        uint64_t p = 0;
-        for (; p <= mask; ++p) {
-            const unsigned long long prev =
-                atomicCAS(reinterpret_cast<unsigned long long *>(&I.table[s].key),
-                          static_cast<unsigned long long>(BT_EMPTY), static_cast<unsigned long long>(k));
-            if (prev == static_cast<unsigned long long>(BT_EMPTY)) {
-                I.table[s].payload = I.dim_attr[i];
-                break;
+        uint64_t s[BT_BUILD_ITEMS];
+        unsigned long long prev[BT_BUILD_ITEMS];
+#pragma unroll
+        for (int c = 0; c < BT_BUILD_ITEMS; ++c) {
+            if (valid[c] && k[c] == BT_EMPTY) {
+                gq_raise(status, GQ_ERR_INVALID_KEY);
+                valid[c] = false;
             }
-            if (prev == static_cast<unsigned long long>(k)) {
-                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
-                break;
-            }
-            s = (s + 1) & mask;
+            s[c] = key_hash(k[c]) >> (64 - L);
+            prev[c] = valid[c] ? atomicCAS(reinterpret_cast<unsigned long long *>(&I.table[s[c]].key),
+                                           static_cast<unsigned long long>(BT_EMPTY),
+                                           static_cast<unsigned long long>(k[c]))
+                               : 0ull;
         }
-        if (p > mask) gq_raise(status, GQ_ERR_CAPACITY);
+#pragma unroll
+        for (int c = 0; c < BT_BUILD_ITEMS; ++c) {
+            if (!valid[c]) continue;
+            uint64_t p = 0;
+            while (true) {
+                if (prev[c] == static_cast<unsigned long long>(BT_EMPTY)) {
+                    I.table[s[c]].payload = pay[c];
+                    break;
+                }
+                if (prev[c] == static_cast<unsigned long long>(k[c])) {
+                    gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                    break;
+                }
+                if (++p > mask) {
+                    gq_raise(status, GQ_ERR_CAPACITY);
+                    break;
+                }
+                s[c] = (s[c] + 1) & mask;
+                prev[c] = atomicCAS(reinterpret_cast<unsigned long long *>(&I.table[s[c]].key),
+                                    static_cast<unsigned long long>(BT_EMPTY), static_cast<unsigned long long>(k[c]));
+            }
+        }
     }
 }
 
 // Fused filter -> probe -> aggregate over one tile of fact rows, walked in
-// chunks of 16 rows per thread; groups accumulate in LDS for the whole tile
-// and are merged into the instance's global group table at its end.
-constexpr int BT_CHUNK_ITEMS = 16;
+// chunks of 8 rows per thread; groups accumulate in LDS for the whole tile
+// and are merged into the instance's global group table at its end.  Each
+// chunk runs in phases over its 8 rows (dates; foreign keys of the kept
+// rows; table slots; value columns of the matches; LDS aggregation), so a
+// phase's loads are all in flight together.
+constexpr int BT_CHUNK_ITEMS = 8;
 constexpr int BT_CHUNK = BT_THREADS * BT_CHUNK_ITEMS;
 
 __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds &T, uint32_t *status)
@@ -296,49 +328,65 @@ __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds
     const int64_t t0 = tile * tile_rows;
     const int64_t t1 = t0 + tile_rows < I.n ? t0 + tile_rows : I.n;
     for (int64_t base = t0; base < t1; base += BT_CHUNK) {
-        int32_t d[BT_CHUNK_ITEMS];
+        bool pass[BT_CHUNK_ITEMS];
+        int64_t k[BT_CHUNK_ITEMS];
 #pragma unroll
         for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
             const int64_t r = base + c * BT_THREADS + threadIdx.x;
-            d[c] = (r < t1) ? I.date[r] : 0;
+            const int32_t d = r < t1 ? I.date[r] : 0;
+            pass[c] = r < t1 && I.date_lo <= d && d < I.date_hi;
         }
 #pragma unroll
         for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
             const int64_t r = base + c * BT_THREADS + threadIdx.x;
-            const bool pass = r < t1 && I.date_lo <= d[c] && d[c] < I.date_hi;
-            bool hit = false;
-            int32_t g = 0;
-            int64_t q = 0;
-            gq_i128 rev{0, 0};
-            if (pass) {
-                const int64_t k = I.fk[r];
-                uint64_t s = key_hash(k) >> (64 - L);
-                for (uint64_t p = 0; p <= mask; ++p) {
-                    const int4 v = *reinterpret_cast<const int4 *>(&I.table[s]);
-                    const int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v.y)) << 32) |
-                                       static_cast<uint32_t>(v.x);
-                    if (sk == k) {
-                        hit = true;
-                        g = v.z;
-                        break;
-                    }
-                    if (sk == BT_EMPTY) break;
-                    s = (s + 1) & mask;
+            k[c] = pass[c] ? I.fk[r] : BT_EMPTY;
+        }
+        uint64_t s[BT_CHUNK_ITEMS];
+        int4 v[BT_CHUNK_ITEMS];
+#pragma unroll
+        for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
+            s[c] = key_hash(k[c]) >> (64 - L);
+            if (pass[c]) v[c] = *reinterpret_cast<const int4 *>(&I.table[s[c]]);
+        }
+        bool hit[BT_CHUNK_ITEMS];
+        int32_t g[BT_CHUNK_ITEMS];
+#pragma unroll
+        for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
+            hit[c] = false;
+            g[c] = 0;
+            if (pass[c]) {
+                int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
+                uint64_t p = 0;
+                while (sk != k[c] && sk != BT_EMPTY && p < mask) {
+                    s[c] = (s[c] + 1) & mask;
+                    v[c] = *reinterpret_cast<const int4 *>(&I.table[s[c]]);
+                    sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
+                    ++p;
                 }
-                if (hit) {
-                    q = I.qty[r];
-                    rev = gq_revenue(I.price[r], I.rev_scale, I.disc[r]);
-                }
+                hit[c] = sk == k[c];
+                g[c] = v[c].z;
             }
-            const int slot = lds_group(T, hit, g);
-            if (hit && slot >= 0) {
+        }
+        int64_t q[BT_CHUNK_ITEMS], pr[BT_CHUNK_ITEMS], ds[BT_CHUNK_ITEMS];
+#pragma unroll
+        for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
+            const int64_t r = base + c * BT_THREADS + threadIdx.x;
+            q[c] = hit[c] ? I.qty[r] : 0;
+            pr[c] = hit[c] ? I.price[r] : 0;
+            ds[c] = hit[c] ? I.disc[r] : 0;
+        }
+#pragma unroll
+        for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
+            const gq_i128 rev = hit[c] ? gq_revenue(pr[c], I.rev_scale, ds[c]) : gq_i128{0, 0};
+            const int slot = lds_group(T, hit[c], g[c]);
+            if (hit[c] && slot >= 0) {
                 atomicAdd(&T.cnt[slot], 1u);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[slot]), static_cast<unsigned long long>(q));
+                atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[slot]), static_cast<unsigned long long>(q[c]));
                 add128(&T.lo[slot], &T.hi[slot], rev, true);
             }
-            const bool spill = hit && slot < 0;
-            const int64_t gs = global_group(I, spill, g, status);
-            if (spill && gs >= 0) global_add(I, gs, 1, static_cast<uint64_t>(q), rev);
+            const bool spill = hit[c] && slot < 0;
+            const int64_t gs = global_group(I, spill, g[c], status);
+            if (spill && gs >= 0) global_add(I, gs, 1, static_cast<uint64_t>(q[c]), rev);
         }
     }
     __syncthreads();
@@ -487,7 +535,7 @@ struct bt_plan {
 
 bool valid_tuning(const gq_tuning &t)
 {
-    return t.load_factor > 0.0 && t.load_factor <= 0.9 && t.probe_tile >= BT_CHUNK && t.probe_tile % BT_CHUNK == 0 &&
+    return t.load_factor > 0.0 && t.load_factor <= 0.9 && t.probe_tile >= 4096 && t.probe_tile % 4096 == 0 &&
            t.probe_tile <= (1 << 22) && t.build_tile >= BT_THREADS && t.build_tile % BT_THREADS == 0 &&
            t.init_tile >= BT_THREADS && t.init_tile % BT_THREADS == 0 && t.lag >= 0 && t.lag <= 1024;
 }
@@ -634,7 +682,8 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
     GQ_TRY(gq_launch(ctx, "gq_batch_zero", batch_zero_counts_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, s,
                      static_cast<const bt_inst *>(d_insts), n_inst));
     if (pl.total_items == 0) return GQ_OK;
-    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(pl.total_items, int64_t(ctx->num_cus) * 2));
+    // three 48 KiB-LDS workgroups fit a CU
+    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(pl.total_items, int64_t(ctx->num_cus) * 3));
     const int nsegs = static_cast<int>(pl.segs.size());
     return gq_launch(ctx, "gq_batch", batch_kernel, dim3(grid), dim3(BT_THREADS), 0, s,
                      static_cast<const bt_inst *>(d_insts), static_cast<const bt_seg *>(d_segs), nsegs,
