@@ -95,9 +95,13 @@ GQ_DEV void signal_done(uint32_t *ctr)
 GQ_DEV uint64_t key_hash(int64_t k) { return gq_fmix64(static_cast<uint64_t>(k)); }
 
 // ---------------------------------------------------------------- groups
+// LDS group table of a probe tile.  A slot is one 64-bit word, 0 = empty,
+// else (key << 32) | 1, claimed and published by a single compare-and-swap.
+// Revenue sums are kept split: lo[] sums the low 32 bits (unsigned) and hi[]
+// the high 32 bits (signed) of each row's revenue, so no accumulation needs a
+// returned value; the slot's revenue is hi * 2^32 + lo (exact for < 2^31 rows).
 struct bt_lds {
-    uint32_t state[BT_LDS_GROUP_SLOTS];
-    int32_t key[BT_LDS_GROUP_SLOTS];
+    uint64_t word[BT_LDS_GROUP_SLOTS];
     uint32_t cnt[BT_LDS_GROUP_SLOTS];
     uint64_t sq[BT_LDS_GROUP_SLOTS];
     uint64_t lo[BT_LDS_GROUP_SLOTS];
@@ -107,7 +111,7 @@ struct bt_lds {
 GQ_DEV void lds_clear(bt_lds &T)
 {
     for (int s = threadIdx.x; s < BT_LDS_GROUP_SLOTS; s += BT_THREADS) {
-        T.state[s] = 0;
+        T.word[s] = 0;
         T.cnt[s] = 0;
         T.sq[s] = 0;
         T.lo[s] = 0;
@@ -121,36 +125,52 @@ GQ_DEV uint64_t group_hash(int32_t k) { return gq_fmix64(static_cast<uint64_t>(s
 GQ_DEV int lds_group(bt_lds &T, bool active, int32_t key)
 {
     uint32_t s = static_cast<uint32_t>(group_hash(key)) & (BT_LDS_GROUP_SLOTS - 1);
+    const unsigned long long want = (static_cast<unsigned long long>(static_cast<uint32_t>(key)) << 32) | 1ull;
     int probes = 0, found = -1;
     bool done = !active;
     while (__any(!done)) {
         if (!done) {
-            uint32_t st = __hip_atomic_load(&T.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (st == 0u) st = atomicCAS(&T.state[s], 0u, 1u);   // claim only an empty slot
-            if (st == 0u) {
-                T.key[s] = key;
-                __threadfence_block();
-                atomicExch(&T.state[s], 2u);
+            unsigned long long *wp = reinterpret_cast<unsigned long long *>(&T.word[s]);
+            unsigned long long w = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (w == 0ull) {
+                w = atomicCAS(wp, 0ull, want);            // claim only an empty slot
+                if (w == 0ull) w = want;
+            }
+            if (w == want) {
                 found = static_cast<int>(s);
                 done = true;
-            } else if (st == 2u) {
-                if (T.key[s] == key) {
-                    found = static_cast<int>(s);
-                    done = true;
-                } else if (++probes >= 64) {
-                    done = true;
-                } else {
-                    s = (s + 1) & (BT_LDS_GROUP_SLOTS - 1);
-                }
+            } else if (++probes >= 64) {
+                done = true;
+            } else {
+                s = (s + 1) & (BT_LDS_GROUP_SLOTS - 1);
             }
         }
     }
     return found;
 }
 
-GQ_DEV void add128(uint64_t *lo, int64_t *hi, gq_i128 v, bool lds)
+// one row into LDS slot s (revenue known to fit 64 bits)
+GQ_DEV void lds_add_row(bt_lds &T, int s, int64_t qty, int64_t rev)
 {
-    (void)lds;
+    atomicAdd(&T.cnt[s], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[s]), static_cast<unsigned long long>(qty));
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[s]),
+              static_cast<unsigned long long>(static_cast<uint32_t>(static_cast<uint64_t>(rev))));
+    const int64_t high = rev >> 32;
+    if (high) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[s]), static_cast<unsigned long long>(high));
+}
+
+GQ_DEV gq_i128 split_total(uint64_t lo_sum, int64_t hi_sum)
+{
+    const __int128 v = static_cast<__int128>(hi_sum) * (static_cast<__int128>(1) << 32) + static_cast<__int128>(lo_sum);
+    gq_i128 r;
+    r.lo = static_cast<uint64_t>(v);
+    r.hi = static_cast<int64_t>(v >> 64);
+    return r;
+}
+
+GQ_DEV void add128(uint64_t *lo, int64_t *hi, gq_i128 v)
+{
     const unsigned long long old =
         atomicAdd(reinterpret_cast<unsigned long long *>(lo), static_cast<unsigned long long>(v.lo));
     const int64_t h = v.hi + ((old + v.lo < old) ? 1 : 0);
@@ -193,7 +213,7 @@ GQ_DEV void global_add(const bt_inst &I, int64_t s, uint64_t cnt, uint64_t sq, g
 {
     atomicAdd(reinterpret_cast<unsigned long long *>(&I.gcnt[s]), static_cast<unsigned long long>(cnt));
     atomicAdd(reinterpret_cast<unsigned long long *>(&I.gsq[s]), static_cast<unsigned long long>(sq));
-    add128(&I.glo[s], &I.ghi[s], rev, false);
+    add128(&I.glo[s], &I.ghi[s], rev);
 }
 
 // ---------------------------------------------------------------- items
@@ -378,28 +398,22 @@ __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds
 #pragma unroll
         for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
             const gq_i128 rev = hit[c] ? gq_revenue(pr[c], I.rev_scale, ds[c]) : gq_i128{0, 0};
-            const int slot = lds_group(T, hit[c], g[c]);
-            if (hit[c] && slot >= 0) {
-                atomicAdd(&T.cnt[slot], 1u);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[slot]), static_cast<unsigned long long>(q[c]));
-                add128(&T.lo[slot], &T.hi[slot], rev, true);
-            }
-            const bool spill = hit[c] && slot < 0;
+            const bool fits = rev.hi == (static_cast<int64_t>(rev.lo) >> 63);
+            const int slot = lds_group(T, hit[c] && fits, g[c]);
+            if (hit[c] && fits && slot >= 0) lds_add_row(T, slot, q[c], static_cast<int64_t>(rev.lo));
+            // a full LDS table or a revenue wider than 64 bits goes to the global table
+            const bool spill = hit[c] && (!fits || slot < 0);
             const int64_t gs = global_group(I, spill, g[c], status);
             if (spill && gs >= 0) global_add(I, gs, 1, static_cast<uint64_t>(q[c]), rev);
         }
     }
     __syncthreads();
     for (int s = threadIdx.x; s < BT_LDS_GROUP_SLOTS; s += BT_THREADS) {
-        const bool occ = T.state[s] == 2u;
-        const int32_t key = occ ? T.key[s] : 0;
+        const uint64_t w = T.word[s];
+        const bool occ = w != 0ull;
+        const int32_t key = static_cast<int32_t>(static_cast<uint32_t>(w >> 32));
         const int64_t gs = global_group(I, occ, key, status);
-        if (occ && gs >= 0) {
-            gq_i128 rv;
-            rv.lo = T.lo[s];
-            rv.hi = T.hi[s];
-            global_add(I, gs, T.cnt[s], T.sq[s], rv);
-        }
+        if (occ && gs >= 0) global_add(I, gs, T.cnt[s], T.sq[s], split_total(T.lo[s], T.hi[s]));
     }
 }
 

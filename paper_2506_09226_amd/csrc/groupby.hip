@@ -214,6 +214,32 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     return found;
 }
 
+// Accumulate one narrow row into slot s with no returned values: the
+// revenue's low 32 bits (unsigned) and high 32 bits (signed) go to separate
+// 64-bit sums, lo[s] and hi[s], exact for up to 2^31 rows per slot
+// (|sum of highs| <= 2^62, sum of lows < 2^63).  The value is
+// hi[s] * 2^32 + lo[s]; lds_split_total() recombines it.  The LDS atomic
+// unit bounds the bucket pass, so a zero high half issues no atomic.
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV void lds_add_split(lds_table<SLOTS, K64, K32> &T, int s, int64_t qty, int64_t rev)
+{
+    atomicAdd(&T.cnt[s], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[s]), static_cast<unsigned long long>(qty));
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[s]),
+              static_cast<unsigned long long>(static_cast<uint32_t>(static_cast<uint64_t>(rev))));
+    const int64_t high = rev >> 32;
+    if (high) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[s]), static_cast<unsigned long long>(high));
+}
+
+GQ_DEV gq_i128 lds_split_total(uint64_t lo_sum, int64_t hi_sum)
+{
+    const __int128 v = static_cast<__int128>(hi_sum) * (static_cast<__int128>(1) << 32) + static_cast<__int128>(lo_sum);
+    gq_i128 r;
+    r.lo = static_cast<uint64_t>(v);
+    r.hi = static_cast<int64_t>(v >> 64);
+    return r;
+}
+
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_add(lds_table<SLOTS, K64, K32> &T, int s, uint32_t cnt, uint64_t qty, gq_i128 rev)
 {
@@ -688,7 +714,7 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
             rev.hi = rv[c] >> 63;
             const uint64_t h = gb_hash(k64[c], k32[c]);
             const int s = lds_find(T, active, h, k64[c], k32[c]);
-            if (active && s >= 0) lds_add(T, s, 1u, static_cast<uint64_t>(q[c]), rev);
+            if (active && s >= 0) lds_add_split(T, s, q[c], rv[c]);
             const bool spill = active && s < 0;
             const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
             if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
@@ -715,8 +741,10 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
         const bool occ = lds_occupied(T, s);
         const int64_t k64 = occ ? lds_key64(T, s) : 0;
         const int32_t k32 = occ ? lds_key32(T, s) : 0;
-        uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0, lo = occ ? T.lo[s] : 0;
-        int64_t hi = occ ? T.hi[s] : 0;
+        uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0;
+        const gq_i128 tot = lds_split_total(occ ? T.lo[s] : 0, occ ? T.hi[s] : 0);
+        uint64_t lo = tot.lo;
+        int64_t hi = tot.hi;
         if (merge) {
             const int64_t gs = g_lookup<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32);
             if (occ && gs >= 0) {

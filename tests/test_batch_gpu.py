@@ -99,6 +99,37 @@ def test_batch_large_instances_use_device_builds(ctx):
         _equal(_sorted(g), _oracle(cols_h, lay, spec))
 
 
+def test_batch_signed_and_wide_revenues(ctx):
+    """Signed quantities and revenues: most fit 64 bits (split LDS sums with
+    negative high halves), a few need more (sent to the global table); group
+    totals pass 2^64.  Equal to the oracle and to the plain form."""
+    spec = synth.BatchSpec(count=8, build_lo=50, build_hi=20_000, seed=synth.SEED_BASE + 93)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    r = np.random.default_rng(93)
+    nt = cols["price"].numel()
+    price = r.integers(1, 1 << 55, size=nt, dtype=np.int64) * np.where(r.random(nt) < 0.4, -1, 1)
+    wide = r.random(nt) < 0.03
+    price[wide] = ((1 << 62) - r.integers(0, 1000, size=int(wide.sum()))) * np.where(r.random(int(wide.sum())) < 0.5,
+                                                                                       -1, 1)
+    cols["price"].copy_(torch.from_numpy(price))
+    cols["qty"].copy_(torch.from_numpy(r.integers(-(1 << 40), 1 << 40, size=nt, dtype=np.int64)))
+    cols["disc"].copy_(torch.from_numpy(r.integers(-20, 11, size=nt).astype(np.int64)))
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    assert ctx.status() == gq.GQ_OK
+    p = PlainPerInstance(ctx, cols, layout, 0, spec.date_hi)
+    p.run()
+    assert ctx.status() == gq.GQ_OK
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    big = False
+    for lay, gb, gp in zip(layout, b.results(), p.results()):
+        e = _oracle(cols_h, lay, spec)
+        big |= any(abs(v) >= 1 << 64 for v in oracle.sum_rev_int(e))
+        _equal(_sorted(gb), e)
+        _equal(_sorted(gp), e)
+    assert big
+
+
 def test_batch_autotune_and_cache(ctx, small_batch, tmp_path):
     spec, cols, layout = small_batch
     b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
