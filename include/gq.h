@@ -82,7 +82,8 @@ const char *gq_last_error(const gq_ctx *ctx);
 
 /* Synchronize `stream`, then read and clear the device status word: *out is
  * GQ_OK or the first device-side error recorded since the last read
- * (GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY or GQ_ERR_CAPACITY).
+ * (GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY, then
+ * GQ_ERR_INVALID_ARG: a table whose header disagrees with its given size).
  * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
 gq_status gq_status_word(gq_ctx *ctx, gq_stream stream, gq_status *out);
 
@@ -201,22 +202,39 @@ gq_status gq_join_probe(gq_ctx *ctx, const void *table, const int64_t *fk,
                         void *ws, size_t ws_bytes, gq_stream stream);
 
 /* Workspace for gq_join_probe_partitioned of at most n rows (about 18 bytes
- * per row plus 72 bytes per 4096 rows). */
+ * per row plus about 530 bytes per 4096 rows). */
 size_t gq_join_probe_partitioned_workspace_bytes(int64_t n);
 
-/* The same join as gq_join_probe, computed as a partitioned probe: the probe
- * rows are first split into 8 lists by fmix64(fk) bits 55..57 (the three
- * bits below the top six) and each XCD of the GPU probes one list, so that
- * for a probe stream in the order of a radix partition by the top 6 or more
- * hash bits each XCD's L2 holds the table slice its list is reading.
+/* The same join as gq_join_probe, computed as a partitioned (radix) join:
+ * the probes of each table region (4096 slots) are answered from an LDS copy
+ * of that region.  Each tile of 4096 probe rows is split, stably, by the
+ * region of its keys (fmix64 bits below the top log2_fanout, up to 256 ways);
+ * one workgroup per region then loads the region into LDS and looks up that
+ * region's rows of every tile; the results are put back in probe order tile
+ * by tile.  Fast when the probe stream is in the order of a radix partition
+ * by the top log2_fanout bits of the same hash (the output of
+ * gq_radix_partition on fk), since then a tile's rows share those bits;
+ * rows that do not are probed in device memory, so any order is correct.
  * Paper: Sec. 2.2 (a local join of inputs partitioned on the key) and the
  * Related Work section (single-GPU query processing, which cites
  * partitioned radix joins).
+ *   table_bytes  the byte size given to gq_join_build for this table; it
+ *                must match the table (checked on the device: a mismatch
+ *                raises GQ_ERR_INVALID_ARG in the status word and leaves
+ *                the output undefined)
+ *   log2_fanout  radix bits of the partition the probe stream is in (0..16;
+ *                0 when it is in no such order)
+ * Tables with fewer than 2^20 slots (cache resident), or too large for 256
+ * regions per partition bucket (more than 2^(log2_fanout + 20) slots), are
+ * probed by gq_join_probe instead.
  * Output: identical to gq_join_probe's (pairs in probe order, *n_out_dev
  * their number).
- * Arguments, errors and capacities as gq_join_probe. */
-gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, const int64_t *fk,
-                                    int64_t n, const int64_t *n_dev, const int32_t *sel,
+ * Other arguments, errors and capacities as gq_join_probe; additionally
+ * GQ_ERR_INVALID_ARG for table_bytes below a 64-slot table or log2_fanout
+ * outside 0..16. */
+gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table_bytes,
+                                    const int64_t *fk, int64_t n, const int64_t *n_dev,
+                                    const int32_t *sel, int log2_fanout,
                                     int32_t *prow_out, int32_t *payload_out, int64_t *n_out_dev,
                                     void *ws, size_t ws_bytes, gq_stream stream);
 

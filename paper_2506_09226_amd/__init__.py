@@ -142,7 +142,7 @@ def lib():
         L.gq_join_probe_partitioned_workspace_bytes.restype = sz
         L.gq_join_probe_partitioned_workspace_bytes.argtypes = [i64]
         L.gq_join_probe_partitioned.restype = st
-        L.gq_join_probe_partitioned.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.gq_join_probe_partitioned.argtypes = [vp, vp, sz, vp, i64, vp, vp, i32, vp, vp, vp, vp, sz, vp]
         L.gq_groupby_workspace_bytes.restype = sz
         L.gq_groupby_workspace_bytes.argtypes = [i64, i64, i32, i32]
         L.gq_groupby_agg.restype = st
@@ -318,10 +318,11 @@ def gq_join_probe(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev
     return prow, payload, n_out
 
 
-def gq_join_probe_partitioned(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev=None, prow=None,
-                              payload=None, n_out=None, ws=None):
-    """Partitioned probe (per-XCD lists); returns (prow_out, payload_out, n_out),
-    identical to gq_join_probe's output."""
+def gq_join_probe_partitioned(ctx: Context, table, fk, sel=None, n: int | None = None, n_dev=None,
+                              log2_fanout: int = 0, prow=None, payload=None, n_out=None, ws=None):
+    """Partitioned (LDS region) probe; returns (prow_out, payload_out, n_out),
+    identical to gq_join_probe's output.  log2_fanout: radix bits of the hash
+    partition the probe stream is in (0 if none)."""
     if n is None:
         n = sel.numel() if sel is not None else fk.numel()
     prow = prow if prow is not None else torch.empty(max(n, 1), dtype=torch.int32, device=ctx.device)
@@ -329,8 +330,9 @@ def gq_join_probe_partitioned(ctx: Context, table, fk, sel=None, n: int | None =
     n_out = n_out if n_out is not None else _i64_scalar(ctx)
     need = lib().gq_join_probe_partitioned_workspace_bytes(n)
     ws = ws if ws is not None else ctx.workspace(need)
-    ctx.check(lib().gq_join_probe_partitioned(ctx.handle, _ptr(table), _ptr(fk), n, _ptr(n_dev), _ptr(sel),
-                                              _ptr(prow), _ptr(payload), _ptr(n_out), _ptr(ws), ws.numel(),
+    ctx.check(lib().gq_join_probe_partitioned(ctx.handle, _ptr(table), table.numel() * table.element_size(),
+                                              _ptr(fk), n, _ptr(n_dev), _ptr(sel), int(log2_fanout), _ptr(prow),
+                                              _ptr(payload), _ptr(n_out), _ptr(ws), ws.numel(),
                                               _stream(ctx.device)))
     return prow, payload, n_out
 

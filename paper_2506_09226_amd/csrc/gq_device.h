@@ -95,6 +95,27 @@ GQ_DEV T gq_block_exclusive_scan(T v, T *total, T *smem)
     return pre + inc - v;
 }
 
+// The same scan with LDS-only barriers (gq_lds_barrier): outstanding global
+// loads and stores of the calling threads stay in flight across it.
+template <int NT, typename T>
+GQ_DEV T gq_block_exclusive_scan_lds(T v, T *total, T *smem)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T inc = gq_wave_inclusive_scan(v);
+    if (lane == 63) smem[wave] = inc;
+    gq_lds_barrier();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        T s = smem[w];
+        pre += (w < wave) ? s : T(0);
+        tot += s;
+    }
+    gq_lds_barrier();
+    *total = tot;
+    return pre + inc - v;
+}
+
 // ---------------------------------------------------------------------------
 // Decoupled look-back over tiles processed in dynamic (atomic-counter) order.
 // Tile status word: bits 62..63 = flag (0 empty, 1 aggregate, 2 inclusive),

@@ -553,6 +553,14 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
     const int64_t base = static_cast<int64_t>(tile) * TILE;
     if (base >= n) return;                          // whole block: uniform
     for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = 0;
+    // this tile's bucket offsets, loaded now so they arrive with the rows
+    constexpr int GPER = GB_MAX_P / GB_THREADS;
+    uint32_t go[GPER];
+#pragma unroll
+    for (int i = 0; i < GPER; ++i) {
+        const int b = threadIdx.x + i * GB_THREADS;
+        go[i] = b < P ? gofs[static_cast<int64_t>(tile) * P + b] : 0u;
+    }
     __syncthreads();
     uint64_t w[ITEMS][W];
     uint32_t pos[ITEMS];
@@ -604,7 +612,11 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = gofs[static_cast<int64_t>(tile) * P + b] - lpos[b];
+#pragma unroll
+    for (int i = 0; i < GPER; ++i) {
+        const int b = threadIdx.x + i * GB_THREADS;
+        if (b < P) lpos[b] = go[i] - lpos[b];
+    }
     __syncthreads();
     const uint32_t words = all * W;                  // rows of this tile that pass the filter
     for (uint32_t e = threadIdx.x; e < words; e += GB_THREADS) {

@@ -454,47 +454,64 @@ __global__ __launch_bounds__(JP_THREADS) void jt_probe_kernel(const void *table,
 
 
 // ------------------------------------------------------------------------
-// Partitioned probe.  The probe rows are split into 8 lists by hash bits
-// 55..57, the three bits just below the top six (so a probe stream already
-// in the order of a radix partition into 64 or more buckets walks, in each
-// list, one 1/512 slice of the table at a time); the workgroups on XCD x
-// probe list x, so each XCD's L2 holds the table slice its list is reading,
-// and the table is read from HBM about once instead of one line per probe.
-//   split:   tile t of 4096 probe rows is regrouped by list (stable) in LDS
-//            and written to pool positions [4096 t, 4096 t + rows) as
-//            (key, index of the row inside the tile); the run of list x in
-//            tile t is chunk (x, t).  No atomics: the pool is dense over [0, n).
-//   probe:   a persistent grid of 8 G workgroups; workgroup b probes list
-//            b mod 8 (its XCD, as workgroups are dispatched round-robin over
-//            the XCDs), taking tiles in groups of 4 with stride 4 G, so the
-//            G workgroups of one XCD sweep one window of consecutive tiles;
-//            each entry's payload, or -1 for a miss, goes to its pool
-//            position.  The assignment is static: no atomics, and every
-//            chunk is probed once whatever the dispatch order.
+// Partitioned probe: the probes of one table region are answered from an LDS
+// copy of that region, and the output order is restored tile by tile.
+//
+// A region is 4096 consecutive table slots (64 KB).  Its id is the top
+// rbits = L - 12 bits of fmix64(key), split as (high part, sub-region): the
+// high part is the top H bits, which a probe stream radix-partitioned by H
+// or more hash bits (the partition operator on the same hash) holds constant
+// along long runs of rows; the sub-region is the next S = rbits - H <= 8 bits.
+//   split:   tile t of 4096 probe rows takes the high part of its first row.
+//            Its rows are regrouped (stable) in LDS into 2^S sub-region lists
+//            plus a stray list (rows of another high part, e.g. where a tile
+//            straddles two partition buckets), and written to pool positions
+//            [4096 t, 4096 t + rows) as (key, index of the row in the tile),
+//            with the list starts of the tile.  Strays are probed right here
+//            against the table in device memory.  The tile range of each high
+//            part is recorded (atomic min / max).
+//   region:  a persistent grid takes regions in order from a counter.  For
+//            region (v, u) a workgroup loads the 4096 slots into LDS, then
+//            walks the tiles of high part v in batches of 256 (one per
+//            thread), gathers the run of list u of every tile, and looks each
+//            key up in LDS; a probe sequence that runs past the region's last
+//            slot continues in device memory, exactly as linear probing does.
+//            The payload, or -1 for a miss, goes to the entry's pool position.
 //   compact: per tile, the results are put back in probe order in LDS (by
 //            the stored in-tile index) and compacted exactly like the
 //            ordered probe (block scan + decoupled look-back).
-// The output is therefore identical to the ordered probe's.
+// The output is therefore identical to the ordered probe's.  Tables with
+// fewer than 2^20 slots (cache resident) or whose regions the tile split
+// cannot separate (rbits - H > 8) take the ordered probe instead.
 // ------------------------------------------------------------------------
-constexpr int JX_LISTS = 8;
-constexpr int JX_SHIFT = 55;
 constexpr int JX_THREADS = 256;
 constexpr int JX_ITEMS = 16;
-constexpr int JX_TILE = JX_THREADS * JX_ITEMS;          // probe rows per split tile / probe round
-constexpr int JX_GROUP = 4;                             // consecutive tiles of one list per probe step
-constexpr int JX_PITEMS = 8;                            // probe entries per thread per round
+constexpr int JX_TILE = JX_THREADS * JX_ITEMS;          // probe rows per split tile
+constexpr int JX_RBITS = 12;                            // region = 4096 slots
+constexpr int JX_REGION = 1 << JX_RBITS;
+constexpr int JX_MAX_S = 8;                             // sub-region bits split per tile
+constexpr int JX_MAX_H = 8;                             // high-part bits (bounds arrays)
+constexpr int JX_LISTS = (1 << JX_MAX_S) + 1;           // sub-region lists + the stray list
+constexpr int JX_STARTS = 260;                          // per tile: list starts (JX_LISTS + 1 used)
+constexpr int JX_WIN = 2048;                            // region kernel: entries per window
 
-struct jx_chunk {
-    uint32_t off, len;
+struct jx_geom {
+    int L;                  // log2 table slots
+    int H;                  // high-part bits
+    int S;                  // sub-region bits
+    int nregions;           // 2^(H + S)
 };
 
 struct jx_ws {
-    uint32_t *ctr;          // [32] compaction tile counter
-    jx_chunk *chunks;       // chunk (x, t) at chunks[x * ntiles + t]
+    uint32_t *ctr;          // [0] region counter, [32] compaction tile counter
+    uint32_t *hp_first;     // per high part: ntiles - first tile (0: none)
+    uint32_t *hp_end;       // per high part: last tile + 1 (0: none)
+    uint64_t *status;       // compaction look-back words, one per tile
+    int32_t *tile_hp;       // high part of each tile's lists, -1 for an empty tile
+    uint16_t *starts;       // per tile: JX_STARTS list starts
     int64_t *skey;          // pool: probe keys
     uint16_t *sidx;         // pool: index of the probe row inside its tile
     int64_t *res;           // pool: payload of the match, -1 for none
-    uint64_t *status;       // compaction look-back words, one per tile
     int64_t ntiles;
 };
 
@@ -504,8 +521,11 @@ jx_ws jx_layout(gq_carver &c, int64_t n)
     const int64_t rows = n > 0 ? n : 1;
     w.ntiles = (rows + JX_TILE - 1) / JX_TILE;
     w.ctr = c.take<uint32_t>(64);
+    w.hp_first = c.take<uint32_t>(1 << JX_MAX_H);
+    w.hp_end = c.take<uint32_t>(1 << JX_MAX_H);
     w.status = c.take<uint64_t>(static_cast<size_t>(w.ntiles));
-    w.chunks = c.take<jx_chunk>(static_cast<size_t>(JX_LISTS * w.ntiles));
+    w.tile_hp = c.take<int32_t>(static_cast<size_t>(w.ntiles));     // first word after the zeroed prefix
+    w.starts = c.take<uint16_t>(static_cast<size_t>(w.ntiles) * JX_STARTS);
     w.skey = c.take<int64_t>(static_cast<size_t>(rows));
     w.sidx = c.take<uint16_t>(static_cast<size_t>(rows));
     w.res = c.take<int64_t>(static_cast<size_t>(rows));
@@ -519,185 +539,308 @@ GQ_DEV int64_t jx_eff_n(int64_t bound, const int64_t *n_dev)
     return d < bound ? (d > 0 ? d : 0) : bound;
 }
 
-GQ_DEV uint32_t jx_list(int64_t key) { return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(key)) >> JX_SHIFT) & 7u; }
+// Linear probing in device memory from slot s; payload or -1.
+GQ_DEV int64_t jx_probe_global(const jt_slot *slots, uint64_t mask, uint64_t s, int64_t k, uint64_t probes)
+{
+    for (; probes <= mask; ++probes) {
+        const int4 v = *reinterpret_cast<const int4 *>(&slots[s]);
+        const int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v.y)) << 32) | static_cast<uint32_t>(v.x);
+        if (sk == k) return static_cast<int64_t>(static_cast<uint32_t>(v.z));
+        if (sk == JT_EMPTY) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
 
-// Stable split of one tile: a row's place is its list's start in the tile,
-// plus the rows of that list in earlier (step, wave) groups, plus its rank
-// among the lanes of its wave with the same list (three ballots, one per
-// list bit).
+// Stable split of one tile.  Rows are wave-contiguous (wave w holds rows
+// [1024 w, 1024 w + 1024) of the tile, item c its rows 64 c + lane); a row's
+// place is its list's start in the tile, plus the rows of that list in
+// earlier waves, plus the rows of that list already seen by its wave, plus
+// its rank among its wave's lanes with the same list (S + 1 ballots).
 template <bool HAS_SEL>
-__global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const int64_t *__restrict__ fk, int64_t n_bound,
-                                                              const int64_t *n_dev, const int32_t *__restrict__ sel,
-                                                              jx_ws w)
+__global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table, const int64_t *__restrict__ fk,
+                                                              int64_t n_bound, const int64_t *n_dev,
+                                                              const int32_t *__restrict__ sel, jx_geom gm, jx_ws w,
+                                                              uint32_t *status)
 {
     constexpr int WAVES = JX_THREADS / 64;
-    __shared__ uint32_t grp[JX_ITEMS * WAVES][JX_LISTS];   // per (step, wave): count, then exclusive prefix
-    __shared__ uint32_t start[JX_LISTS + 1];
+    constexpr int WROWS = JX_TILE / WAVES;
+    __shared__ uint32_t wcnt[WAVES][JX_LISTS];            // per wave: running counts, then prefixes
+    __shared__ uint32_t lstart[2 * JX_THREADS + 1];
+    __shared__ uint32_t scan_smem[WAVES];
     __shared__ int64_t stage_k[JX_TILE];
     __shared__ uint16_t stage_i[JX_TILE];
+    __shared__ int32_t s_hp;
     const int64_t n = jx_eff_n(n_bound, n_dev);
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * JX_TILE;
+    const int64_t rows = n - base < JX_TILE ? n - base : JX_TILE;
+    const bool bad_table = static_cast<const jt_header *>(table)->log2_slots != static_cast<uint32_t>(gm.L);
+    if (rows <= 0 || bad_table) {                          // uniform: a tile past the end, or a wrong table size
+        if (threadIdx.x == 0) {
+            w.tile_hp[tile] = -1;
+            if (bad_table) gq_raise(status, GQ_ERR_INVALID_ARG);
+        }
+        return;
+    }
+    const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
+    const uint64_t mask = (1ull << gm.L) - 1;
+    const int rbits = gm.L - JX_RBITS;
+    const uint32_t stray = 1u << gm.S;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t k[JX_ITEMS];
+    for (int i = threadIdx.x; i < WAVES * JX_LISTS; i += JX_THREADS) (&wcnt[0][0])[i] = 0;
     int32_t r[JX_ITEMS];
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t e = base + c * JX_THREADS + threadIdx.x;
+        const int q = wave * WROWS + c * 64 + lane;          // index in the tile
         r[c] = 0;
-        if (e < n) r[c] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
+        if (q < rows) r[c] = HAS_SEL ? sel[base + q] : static_cast<int32_t>(base + q);
     }
+    int64_t k[JX_ITEMS];
+    uint32_t reg[JX_ITEMS];
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t e = base + c * JX_THREADS + threadIdx.x;
-        k[c] = e < n ? fk[r[c]] : 0;
+        const int q = wave * WROWS + c * 64 + lane;
+        k[c] = q < rows ? fk[r[c]] : 0;
+        reg[c] = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - rbits));
     }
-    uint32_t rank[JX_ITEMS];
-    uint8_t lst[JX_ITEMS];
+    if (threadIdx.x == 0) s_hp = static_cast<int32_t>(reg[0] >> gm.S);
+    __syncthreads();
+    const uint32_t hp = static_cast<uint32_t>(s_hp);
+    uint32_t pos[JX_ITEMS];                               // list << 16 | rank in (wave, list)
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t e = base + c * JX_THREADS + threadIdx.x;
-        const bool valid = e < n;
-        const uint32_t x = valid ? jx_list(k[c]) : 0u;
-        const uint64_t act = gq_ballot(valid);
-        const uint64_t b0 = gq_ballot(valid && (x & 1u)), b1 = gq_ballot(valid && (x & 2u)),
-                       b2 = gq_ballot(valid && (x & 4u));
-        const uint64_t peers = act & ((x & 1u) ? b0 : ~b0) & ((x & 2u) ? b1 : ~b1) & ((x & 4u) ? b2 : ~b2);
-        rank[c] = gq_mbcnt(peers);
-        lst[c] = static_cast<uint8_t>(x);
-        if (lane < JX_LISTS) {
-            const uint32_t l = static_cast<uint32_t>(lane);
-            const uint64_t ml = act & ((l & 1u) ? b0 : ~b0) & ((l & 2u) ? b1 : ~b1) & ((l & 4u) ? b2 : ~b2);
-            grp[c * WAVES + wave][l] = static_cast<uint32_t>(__popcll(ml));
+        const int q = wave * WROWS + c * 64 + lane;
+        const bool valid = q < rows;
+        const uint32_t x = (reg[c] >> gm.S) == hp ? (reg[c] & (stray - 1)) : stray;
+        uint64_t match = gq_ballot(valid);
+        for (int bit = 0; bit <= gm.S; ++bit) {
+            const bool set = (x >> bit) & 1u;
+            const uint64_t bal = gq_ballot(valid && set);
+            match &= set ? bal : ~bal;
         }
+        const uint32_t below = gq_mbcnt(match);
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(match));
+        uint32_t old = 0;
+        if (valid) old = wcnt[wave][x];
+        if (valid && below == cnt - 1) wcnt[wave][x] = old + cnt;
+        pos[c] = (x << 16) | (old + below);
     }
     __syncthreads();
-    if (threadIdx.x < JX_LISTS) {                     // per list: prefix over (step, wave) in row order
+    // per list: prefix over waves; thread i owns lists 2i and 2i + 1
+    uint32_t tot[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int x = 2 * threadIdx.x + j;
         uint32_t run = 0;
-        for (int g = 0; g < JX_ITEMS * WAVES; ++g) {
-            const uint32_t c = grp[g][threadIdx.x];
-            grp[g][threadIdx.x] = run;
-            run += c;
+        if (x < JX_LISTS) {
+#pragma unroll
+            for (int v = 0; v < WAVES; ++v) {
+                const uint32_t t = wcnt[v][x];
+                wcnt[v][x] = run;
+                run += t;
+            }
         }
-        start[threadIdx.x] = run;                    // list total, turned into a start below
+        tot[j] = run;
     }
+    uint32_t all;
+    const uint32_t excl = gq_block_exclusive_scan<JX_THREADS>(tot[0] + tot[1], &all, scan_smem);
+    lstart[2 * threadIdx.x] = excl;
+    lstart[2 * threadIdx.x + 1] = excl + tot[0];
+    if (threadIdx.x == 0) lstart[2 * JX_THREADS] = all;
     __syncthreads();
+    for (uint32_t x = threadIdx.x; x <= stray + 1; x += JX_THREADS)
+        w.starts[tile * JX_STARTS + x] = static_cast<uint16_t>(lstart[x]);
     if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int x = 0; x < JX_LISTS; ++x) {
-            const uint32_t c = start[x];
-            start[x] = run;
-            run += c;
-        }
-        start[JX_LISTS] = run;
-    }
-    __syncthreads();
-    if (threadIdx.x < JX_LISTS) {                     // every chunk is written, empty ones too
-        jx_chunk ch;
-        ch.off = static_cast<uint32_t>(base) + start[threadIdx.x];
-        ch.len = start[threadIdx.x + 1] - start[threadIdx.x];
-        w.chunks[static_cast<int64_t>(threadIdx.x) * w.ntiles + tile] = ch;
+        w.tile_hp[tile] = static_cast<int32_t>(hp);
+        atomicMax(&w.hp_first[hp], static_cast<uint32_t>(w.ntiles - tile));
+        atomicMax(&w.hp_end[hp], static_cast<uint32_t>(tile + 1));
     }
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t e = base + c * JX_THREADS + threadIdx.x;
-        if (e < n) {
-            const uint32_t x = lst[c];
-            const uint32_t q = start[x] + grp[c * WAVES + wave][x] + rank[c];
-            stage_k[q] = k[c];
-            stage_i[q] = static_cast<uint16_t>(c * JX_THREADS + threadIdx.x);
+        const int q = wave * WROWS + c * 64 + lane;
+        if (q < rows) {
+            const uint32_t x = pos[c] >> 16;
+            const uint32_t p = lstart[x] + wcnt[wave][x] + (pos[c] & 0xffffu);
+            stage_k[p] = k[c];
+            stage_i[p] = static_cast<uint16_t>(q);
+            if (x == stray) {                              // probed here, in device memory
+                const uint64_t s = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - gm.L);
+                w.res[base + p] = k[c] == JT_EMPTY ? -1 : jx_probe_global(slots, mask, s, k[c], 0);
+            }
         }
     }
     __syncthreads();
-    const uint32_t total = start[JX_LISTS];
-    for (uint32_t q = threadIdx.x; q < total; q += JX_THREADS) {
+    for (uint32_t q = threadIdx.x; q < static_cast<uint32_t>(rows); q += JX_THREADS) {
         w.skey[base + q] = stage_k[q];
         w.sidx[base + q] = stage_i[q];
     }
 }
 
-__global__ __launch_bounds__(JX_THREADS) void jx_probe_kernel(const void *table, jx_ws w, int per_list)
+// Region probes from LDS (see above).  Persistent: regions come from w.ctr[0].
+__global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table, jx_geom gm, jx_ws w)
 {
-    __shared__ uint32_t c_off[JX_GROUP], c_end[JX_GROUP + 1];
-    const jt_header *hdr = static_cast<const jt_header *>(table);
-    const int L = static_cast<int>(hdr->log2_slots);
-    const uint64_t mask = (1ull << L) - 1;
+    __shared__ __align__(16) int64_t lkey[JX_REGION];
+    __shared__ int32_t lpay[JX_REGION];
+    __shared__ uint8_t map[JX_WIN];                       // window entry -> batch tile (thread)
+    __shared__ int32_t b_at[JX_THREADS];                  // pool position of each batch tile's run
+    __shared__ uint32_t b_pos[JX_THREADS];                // exclusive prefix of the runs' lengths
+    __shared__ uint32_t scan_smem[JX_THREADS / 64];
+    __shared__ int64_t s_item;
+    if (static_cast<const jt_header *>(table)->log2_slots != static_cast<uint32_t>(gm.L)) return;   // uniform
     const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
-    const uint32_t x = blockIdx.x % JX_LISTS;
-    const int64_t stride = static_cast<int64_t>(per_list) * JX_GROUP;
-    for (int64_t t0 = static_cast<int64_t>(blockIdx.x / JX_LISTS) * JX_GROUP; t0 < w.ntiles; t0 += stride) {
-        const uint32_t ng = static_cast<uint32_t>(w.ntiles - t0 < JX_GROUP ? w.ntiles - t0 : JX_GROUP);
-        __syncthreads();                                  // the previous group is done with c_off / c_end
-        if (threadIdx.x < ng) {
-            const jx_chunk ch = w.chunks[static_cast<int64_t>(x) * w.ntiles + t0 + threadIdx.x];
-            c_off[threadIdx.x] = ch.off;
-            c_end[threadIdx.x + 1] = ch.len;
-        }
+    const uint64_t mask = (1ull << gm.L) - 1;
+    // As in every persistent loop here, a barrier opens each pass so the
+    // thread-0 dequeue never merges with thread-0 work of the previous pass.
+    while (true) {
         __syncthreads();
-        if (threadIdx.x == 0) {
-            c_end[0] = 0;
-            for (uint32_t j = 1; j <= ng; ++j) c_end[j] += c_end[j - 1];
-        }
+        if (threadIdx.x == 0) s_item = static_cast<int64_t>(atomicAdd(&w.ctr[0], 1u));
         __syncthreads();
-        uint32_t e1 = c_end[1], e2 = c_end[2], e3 = c_end[3];
-        const uint32_t total = c_end[ng];
-        for (uint32_t r0 = 0; r0 < total; r0 += JX_THREADS * JX_PITEMS) {
-            int64_t k[JX_PITEMS];
-            int64_t at[JX_PITEMS];
-            uint64_t s[JX_PITEMS];
-            int4 v[JX_PITEMS];
-#pragma unroll
-            for (int c = 0; c < JX_PITEMS; ++c) {
-                const uint32_t q = r0 + c * JX_THREADS + threadIdx.x;
-                k[c] = JT_EMPTY;
-                at[c] = -1;
-                if (q < total) {
-                    const uint32_t j = (q >= e1 ? 1u : 0u) + (ng > 2 && q >= e2 ? 1u : 0u) + (ng > 3 && q >= e3 ? 1u : 0u);
-                    at[c] = static_cast<int64_t>(c_off[j]) + (q - c_end[j]);
-                    k[c] = w.skey[at[c]];
+        const int64_t item = gq_uniform(s_item);
+        if (item >= gm.nregions) break;
+        const uint32_t hp = static_cast<uint32_t>(item) >> gm.S;
+        const uint32_t sub = static_cast<uint32_t>(item) & ((1u << gm.S) - 1);
+        const jt_slot *rs = slots + (static_cast<uint64_t>(item) << JX_RBITS);
+        for (int j = threadIdx.x; j < JX_REGION; j += JX_THREADS) {
+            const int4 v = *reinterpret_cast<const int4 *>(&rs[j]);
+            lkey[j] = (static_cast<int64_t>(static_cast<uint32_t>(v.y)) << 32) | static_cast<uint32_t>(v.x);
+            lpay[j] = v.z;
+        }
+        const uint32_t first_c = w.hp_first[hp], end = w.hp_end[hp];
+        const int64_t t_lo = gq_uniform(first_c ? w.ntiles - static_cast<int64_t>(first_c) : 0);
+        const int64_t t_hi = gq_uniform(static_cast<int64_t>(end));
+        // the run of list `sub` in tile t (length 0 if t is not a tile of this high part)
+        auto run_of = [&](int64_t t, uint32_t &len, int32_t &at) {
+            len = 0;
+            at = 0;
+            if (t < t_hi) {
+                const int32_t thp = w.tile_hp[t];
+                const uint32_t a = w.starts[t * JX_STARTS + sub], b = w.starts[t * JX_STARTS + sub + 1];
+                if (thp == static_cast<int32_t>(hp)) {
+                    len = b - a;
+                    at = static_cast<int32_t>(t * JX_TILE + a);
                 }
             }
+        };
+        uint32_t len;
+        int32_t at;
+        run_of(t_lo + threadIdx.x, len, at);
+        // Communication inside the item goes through LDS only, so its barriers
+        // order LDS alone: the region's loads, the next batch's run lookups
+        // and the result stores stay in flight across them.
+        gq_lds_barrier();                                  // the region is in LDS
+        for (int64_t t0 = t_lo; t0 < t_hi; t0 += JX_THREADS) {
+            uint32_t nlen;
+            int32_t nat;
+            run_of(t0 + JX_THREADS + threadIdx.x, nlen, nat);      // next batch, in flight meanwhile
+            uint32_t total;
+            const uint32_t pos = gq_block_exclusive_scan_lds<JX_THREADS>(len, &total, scan_smem);
+            b_at[threadIdx.x] = at;
+            b_pos[threadIdx.x] = pos;
+            const uint32_t ntot = static_cast<uint32_t>(gq_uniform(total));
+            for (uint32_t w0 = 0; w0 < ntot; w0 += JX_WIN) {
+                gq_lds_barrier();                          // previous window done with map; b_* written
+                const uint32_t a = pos > w0 ? pos : w0;
+                const uint32_t e = (pos + len < w0 + JX_WIN) ? pos + len : w0 + JX_WIN;
+                for (uint32_t j = a; j < e; ++j) map[j - w0] = static_cast<uint8_t>(threadIdx.x);
+                gq_lds_barrier();
+                const uint32_t cnt = ntot - w0 < JX_WIN ? ntot - w0 : JX_WIN;
+                constexpr int PER = JX_WIN / JX_THREADS;
+                int64_t k[PER];
+                int32_t pa[PER];
 #pragma unroll
-            for (int c = 0; c < JX_PITEMS; ++c) {
-                s[c] = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - L);
-                v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
-            }
-#pragma unroll
-            for (int c = 0; c < JX_PITEMS; ++c) {
-                if (at[c] < 0) continue;
-                int64_t out = -1;
-                if (k[c] != JT_EMPTY) {
-                    int64_t sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) |
-                                 static_cast<uint32_t>(v[c].x);
-                    uint64_t probes = 0;
-                    while (sk != k[c] && sk != JT_EMPTY && probes < mask) {
-                        s[c] = (s[c] + 1) & mask;
-                        v[c] = *reinterpret_cast<const int4 *>(&slots[s[c]]);
-                        sk = (static_cast<int64_t>(static_cast<uint32_t>(v[c].y)) << 32) | static_cast<uint32_t>(v[c].x);
-                        ++probes;
+                for (int c = 0; c < PER; ++c) {
+                    const uint32_t q = c * JX_THREADS + threadIdx.x;
+                    pa[c] = -1;
+                    k[c] = JT_EMPTY;
+                    if (q < cnt) {
+                        const int i = map[q];
+                        pa[c] = b_at[i] + static_cast<int32_t>(w0 + q - b_pos[i]);
+                        k[c] = w.skey[pa[c]];
                     }
-                    if (sk == k[c]) out = static_cast<int64_t>(static_cast<uint32_t>(v[c].z));
                 }
-                w.res[at[c]] = out;
+                // A probe step reads the aligned group of four slots that holds
+                // the current slot (two 16-byte LDS reads).  The first step of
+                // all PER probes is issued together; the few probes not settled
+                // by it walk on one by one.  Payloads are read after all probes.
+                int32_t hs[PER];                       // slot of the match, -1 none, -2 ran past the region
+                uint32_t sl[PER];
+                longlong2 q0[PER], q1[PER];
+#pragma unroll
+                for (int c = 0; c < PER; ++c) {
+                    const uint64_t home = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - gm.L);
+                    sl[c] = static_cast<uint32_t>(home) & (JX_REGION - 1);
+                    const uint32_t g = sl[c] & ~3u;
+                    q0[c] = *reinterpret_cast<const longlong2 *>(&lkey[g]);
+                    q1[c] = *reinterpret_cast<const longlong2 *>(&lkey[g + 2]);
+                }
+#pragma unroll
+                for (int c = 0; c < PER; ++c) {
+                    hs[c] = -1;
+                    if (pa[c] < 0 || k[c] == JT_EMPTY) continue;
+                    while (true) {
+                        const uint32_t g = sl[c] & ~3u;
+                        const int64_t v[4] = {q0[c].x, q0[c].y, q1[c].x, q1[c].y};
+                        uint32_t eq = 0, em = 0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            eq |= (v[j] == k[c] ? 1u : 0u) << j;
+                            em |= (v[j] == JT_EMPTY ? 1u : 0u) << j;
+                        }
+                        const uint32_t stop = (eq | em) & (~0u << (sl[c] & 3u)) & 0xfu;
+                        if (stop) {
+                            const uint32_t j = static_cast<uint32_t>(__builtin_ctz(stop));
+                            if ((eq >> j) & 1u) hs[c] = static_cast<int32_t>(g + j);
+                            break;
+                        }
+                        sl[c] = g + 4;
+                        if (sl[c] == JX_REGION) {
+                            hs[c] = -2;
+                            break;
+                        }
+                        q0[c] = *reinterpret_cast<const longlong2 *>(&lkey[sl[c]]);
+                        q1[c] = *reinterpret_cast<const longlong2 *>(&lkey[sl[c] + 2]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < PER; ++c) {
+                    if (pa[c] < 0) continue;
+                    int64_t out = hs[c] >= 0 ? static_cast<int64_t>(static_cast<uint32_t>(lpay[hs[c]])) : -1;
+                    if (hs[c] == -2) {                       // continue in device memory, as linear probing does
+                        const uint64_t home = gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - gm.L);
+                        out = jx_probe_global(slots, mask, ((static_cast<uint64_t>(item) + 1) << JX_RBITS) & mask,
+                                              k[c], JX_REGION - (static_cast<uint32_t>(home) & (JX_REGION - 1)));
+                    }
+                    w.res[pa[c]] = out;
+                }
             }
+            gq_lds_barrier();                              // b_at / b_pos / map free for the next batch
+            len = nlen;
+            at = nat;
         }
     }
 }
 
-// Per tile: results back in probe order (one 8-byte LDS word per entry,
-// scattered by the in-tile index), then the ordered compaction of the matches.
+// Per tile: results back in probe order in LDS (payload words plus a hit
+// bitmap, scattered by the stored in-tile index), then the ordered compaction
+// of the matches (block scan + decoupled look-back).  Only the in-tile index
+// of each match is staged; its row id is read from the selection as it is
+// written out.  About 25 KB of LDS, so six workgroups share a CU.
 template <bool HAS_SEL>
 __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t n_bound, const int64_t *n_dev,
                                                                 const int32_t *__restrict__ sel,
                                                                 int32_t *__restrict__ prow_out,
                                                                 int32_t *__restrict__ pay_out, int64_t *n_out)
 {
-    __shared__ int64_t by_idx[JX_TILE];                   // payload or -1 in probe order; then the staged pairs
+    __shared__ int32_t pay[JX_TILE];                      // payloads in probe order; then the staged payloads
+    __shared__ uint16_t stage_i[JX_TILE];                 // in-tile index of each staged match
+    __shared__ uint32_t hitw[JX_TILE / 32];               // hit bitmap in probe order
     __shared__ uint32_t scan_smem[JX_THREADS / 64];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_goff;
     const int64_t n = jx_eff_n(n_bound, n_dev);
     if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctr[32], 1u);
+    if (threadIdx.x < JX_TILE / 32) hitw[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t t = s_tile;
     const int64_t ntiles = (n + JX_TILE - 1) / JX_TILE;
@@ -708,49 +851,55 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
     const int64_t base = static_cast<int64_t>(t) * JX_TILE;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t rows = n - base < JX_TILE ? n - base : JX_TILE;
-    // thread i owns probe-order elements [16 i, 16 i + 16): their rows, loaded now
-    const int elem0 = threadIdx.x * JX_ITEMS;
-    int32_t my_row[JX_ITEMS];
-#pragma unroll
-    for (int i = 0; i < JX_ITEMS; ++i) {
-        const int64_t e = base + elem0 + i;
-        my_row[i] = e < n ? (HAS_SEL ? sel[e] : static_cast<int32_t>(e)) : 0;
-    }
+    uint16_t ix[JX_ITEMS];
+    int64_t rv[JX_ITEMS];
 #pragma unroll
     for (int c = 0; c < JX_ITEMS; ++c) {
         const int64_t p = base + c * JX_THREADS + threadIdx.x;     // pool position
-        if (p < n) by_idx[w.sidx[p]] = w.res[p];
+        ix[c] = 0;
+        rv[c] = -1;
+        if (p < n) {
+            ix[c] = static_cast<uint16_t>(w.sidx[p] & (JX_TILE - 1));
+            rv[c] = w.res[p];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < JX_ITEMS; ++c) {
+        const int64_t p = base + c * JX_THREADS + threadIdx.x;
+        if (p < n) {
+            pay[ix[c]] = static_cast<int32_t>(rv[c]);
+            if (rv[c] >= 0) atomicOr(&hitw[ix[c] >> 5], 1u << (ix[c] & 31));
+        }
     }
     __syncthreads();
-    uint32_t mine = 0;
+    // thread i owns probe-order elements [16 i, 16 i + 16)
+    const int elem0 = threadIdx.x * JX_ITEMS;
+    uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & 0xffffu;
+    if (elem0 + JX_ITEMS > rows) mine &= rows > elem0 ? (1u << (rows - elem0)) - 1 : 0u;
     int32_t my_pay[JX_ITEMS];
 #pragma unroll
-    for (int i = 0; i < JX_ITEMS; ++i) {
-        const int64_t rv = elem0 + i < rows ? by_idx[elem0 + i] : -1;
-        mine |= rv >= 0 ? (1u << i) : 0u;
-        my_pay[i] = static_cast<int32_t>(rv);
-    }
+    for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[elem0 + i];
     uint32_t total;
     uint32_t pos = gq_block_exclusive_scan<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
     if (wave == 0) {
         const uint64_t g = gq_lookback(w.status, t, total);
         if (lane == 0) s_goff = g;
     }
-    int32_t *stage_row = reinterpret_cast<int32_t *>(by_idx);
-    int32_t *stage_pay = stage_row + JX_TILE;
+    // the scan's barriers ordered every read of pay[] before these writes
 #pragma unroll
     for (int i = 0; i < JX_ITEMS; ++i) {
         if (mine & (1u << i)) {
-            stage_row[pos] = my_row[i];
-            stage_pay[pos] = my_pay[i];
+            stage_i[pos] = static_cast<uint16_t>(elem0 + i);
+            pay[pos] = my_pay[i];
             ++pos;
         }
     }
     __syncthreads();
     const int64_t goff = static_cast<int64_t>(s_goff);
     for (uint32_t i = threadIdx.x; i < total; i += JX_THREADS) {
-        prow_out[goff + i] = stage_row[i];
-        pay_out[goff + i] = stage_pay[i];
+        const int64_t e = base + stage_i[i];
+        prow_out[goff + i] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
+        pay_out[goff + i] = pay[i];
     }
     if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
 }
@@ -850,35 +999,50 @@ size_t gq_join_probe_partitioned_workspace_bytes(int64_t n)
     return c.bytes();
 }
 
-gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, const int64_t *fk, int64_t n,
-                                    const int64_t *n_dev, const int32_t *sel, int32_t *prow_out,
-                                    int32_t *payload_out, int64_t *n_out_dev, void *ws, size_t ws_bytes,
-                                    gq_stream stream)
+gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table_bytes, const int64_t *fk,
+                                    int64_t n, const int64_t *n_dev, const int32_t *sel, int log2_fanout,
+                                    int32_t *prow_out, int32_t *payload_out, int64_t *n_out_dev, void *ws,
+                                    size_t ws_bytes, gq_stream stream)
 {
     if (!ctx) return GQ_ERR_INVALID_ARG;
     if (n < 0 || n > GQ_MAX_ROWS)
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: n=%lld", (long long)n);
     if (!table || (!fk && n > 0) || !prow_out || !payload_out || !n_out_dev)
         return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: NULL table, fk, output or count");
+    if (table_bytes < JT_HEADER + 64 * sizeof(jt_slot))
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: table of %zu bytes is too small",
+                       table_bytes);
+    if (log2_fanout < 0 || log2_fanout > 16)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_join_probe_partitioned: log2_fanout=%d", log2_fanout);
     const size_t need = gq_join_probe_partitioned_workspace_bytes(n);
     if (!ws || ws_bytes < need)
         return gq_fail(ctx, GQ_ERR_WORKSPACE, "gq_join_probe_partitioned: workspace %zu < %zu bytes", ws_bytes,
                        need);
+    jx_geom gm{};
+    gm.L = table_log2_from_bytes(table_bytes);
+    const int rbits = gm.L - JX_RBITS;
+    gm.H = std::min(std::min(log2_fanout, JX_MAX_H), std::max(rbits, 0));
+    gm.S = rbits - gm.H;
+    gm.nregions = rbits > 0 ? 1 << rbits : 1;
+    // cache-resident tables, or regions the tile split cannot separate: the ordered probe
+    if (rbits < 8 || gm.S > JX_MAX_S)
+        return gq_join_probe(ctx, table, fk, n, n_dev, sel, prow_out, payload_out, n_out_dev, ws, ws_bytes, stream);
     hipStream_t s = static_cast<hipStream_t>(stream);
     gq_carver c(ws);
     jx_ws w = jx_layout(c, n);
-    // counters and look-back words (the prefix of the workspace up to the chunk table)
-    GQ_TRY(gq_zero(ctx, ws, static_cast<size_t>(reinterpret_cast<char *>(w.chunks) - static_cast<char *>(ws)) / 4, s));
+    // counters, tile bounds and look-back words (the prefix up to the tile table)
+    GQ_TRY(gq_zero(ctx, ws, static_cast<size_t>(reinterpret_cast<char *>(w.tile_hp) - static_cast<char *>(ws)) / 4, s));
     const uint32_t tiles = static_cast<uint32_t>(w.ntiles);
     if (sel)
-        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s, fk,
-                         n, n_dev, sel, w));
+        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s, table,
+                         fk, n, n_dev, sel, gm, w, ctx->status_dev));
     else
         GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s,
-                         fk, n, n_dev, sel, w));
-    const int per_list = ctx->num_cus / 2;                  // 4 workgroups per CU in all
-    GQ_TRY(gq_launch(ctx, "gq_join_probe_lists", jx_probe_kernel, dim3(static_cast<uint32_t>(per_list * JX_LISTS)),
-                     dim3(JX_THREADS), 0, s, table, w, per_list));
+                         table, fk, n, n_dev, sel, gm, w, ctx->status_dev));
+    const int64_t want = static_cast<int64_t>(ctx->num_cus) * 3;      // three 52-KB-LDS workgroups per CU
+    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(want, gm.nregions));
+    GQ_TRY(gq_launch(ctx, "gq_join_probe_regions", jx_region_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, gm,
+                     w));
     if (sel)
         return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s,
                          w, n, n_dev, sel, prow_out, payload_out, n_out_dev);

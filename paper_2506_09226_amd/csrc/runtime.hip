@@ -100,7 +100,7 @@ gq_status gq_status_word(gq_ctx *ctx, gq_stream stream, gq_status *out)
     GQ_CHECK_HIP(ctx, hipMemcpyAsync(&bits, ctx->status_dev, sizeof bits, hipMemcpyDeviceToHost, s));
     GQ_CHECK_HIP(ctx, hipStreamSynchronize(s));
     *out = GQ_OK;
-    const int order[] = {GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY};
+    const int order[] = {GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY, GQ_ERR_INVALID_ARG};
     for (int c : order)
         if (bits & (1u << c)) {
             *out = c;

@@ -4,9 +4,11 @@
     ->  probe(partitioned fk via the selection)  ->  group-by(dim attribute)
     ->  float64 averages  [->  top-k of price over the selection]
 
-The probe is the single-pass one (gq_join_probe, the default: faster on
-MI355X at every measured shape) or the partitioned one
-(gq_join_probe_partitioned); both give the same output.
+The probe is the single-pass one (gq_join_probe) or the partitioned one
+(gq_join_probe_partitioned: table regions probed from LDS); both give the
+same output.  "auto" takes the partitioned probe when the fact table was
+radix-partitioned (then the probe stream is in region order), otherwise the
+single-pass one.
 
 All buffers and workspaces are allocated once, so a step allocates nothing and
 never waits for the host: every count travels on the device.
@@ -47,7 +49,7 @@ class PlainPipeline:
         self.pay = torch.empty(max(n, 1), dtype=torch.int32, device=d)
         self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
         if probe == "auto":
-            probe = "ordered"
+            probe = "partitioned" if partition else "ordered"
         if probe not in ("ordered", "partitioned"):
             raise ValueError(f"probe must be auto, ordered or partitioned, not {probe!r}")
         self.probe = probe
@@ -77,9 +79,13 @@ class PlainPipeline:
         fk, date, qty, price, disc = self.columns()
         gq_filter(ctx, date, -(1 << 31), self.date_hi, out=self.sel, n_out=self.n_sel, ws=self.ws_filter)
         gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table, ws=self.ws_build)
-        probe = gq_join_probe_partitioned if self.probe == "partitioned" else gq_join_probe
-        probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow, payload=self.pay,
-              n_out=self.n_join, ws=self.ws_probe)
+        if self.probe == "partitioned":
+            gq_join_probe_partitioned(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel,
+                                      log2_fanout=self.log2p if self.partition else 0, prow=self.prow,
+                                      payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
+        else:
+            gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
+                          payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
         gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,
                        max_groups=self.max_groups, out=self.groups, ws=self.ws_gb)
         if self.k:

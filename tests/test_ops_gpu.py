@@ -211,24 +211,33 @@ def test_join_empty_sides(ctx):
     assert int(cnt.item()) == 0
 
 
-@pytest.mark.parametrize("m,n,order", [(1000, 1, "random"), (60_000, 300_001, "random"),
-                                       (2_000_000, 3_000_000, "partitioned"), (2_000_000, 1_000_000, "random")])
-def test_join_probe_partitioned(ctx, m, n, order):
+@pytest.mark.parametrize("m,n,order,fanout,lf", [
+    (1000, 1, "random", 0, 0.5),                 # cache-resident table: the ordered probe
+    (60_000, 300_001, "random", 6, 0.5),         # cache-resident table: the ordered probe
+    (2_000_000, 3_000_000, "partitioned", 6, 0.5),   # 2^22 slots: 64 x 16 regions
+    (700_000, 2_000_000, "partitioned", 6, 0.5),     # 2^21 slots: 64 x 8 regions
+    (400_000, 1_000_000, "random", 0, 0.5),      # 2^20 slots, no high part: 256 regions, any order
+    (2_000_000, 1_000_000, "random", 6, 0.5),    # wrong order for the hint: nearly all rows stray
+    (2_000_000, 1_000_000, "random", 2, 0.5),    # 4 high parts: three quarters stray
+    (1_800_000, 2_500_000, "partitioned", 6, 0.9),   # long probe runs: many cross a region's end
+])
+def test_join_probe_partitioned(ctx, m, n, order, fanout, lf):
     """The partitioned probe returns exactly the output of the ordered probe
     (the oracle, in probe order): with and without a selection, with misses,
     with a device count, on a probe stream in radix-partition order and on a
-    random one."""
-    r = rng(m + 7 * n)
+    random one, with regions held in LDS and with the fallbacks."""
+    r = rng(m + 7 * n + fanout)
     bkey, bpay = _dim(m, m + 3)
     fk = np.where(r.random(n) < 0.85, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
     fk = fk.astype(np.int64)
-    if order == "partitioned":                 # stable order by the top 6 hash bits, as after the partition
-        fk = fk[np.argsort(_fmix64_np(fk) >> np.uint64(58), kind="stable")]
-    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay))
+    if order == "partitioned":                 # stable order by the top `fanout` hash bits, as after the partition
+        fk = fk[np.argsort(_fmix64_np(fk) >> np.uint64(64 - fanout), kind="stable")]
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), load_factor=lf)
     sel = np.sort(r.choice(n, size=(2 * n) // 3, replace=False)).astype(np.int32)
     for s in (None, sel):
         ep, ey = oracle.join(bkey, bpay, fk, s)
-        prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=None if s is None else dev(s))
+        prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=None if s is None else dev(s),
+                                                      log2_fanout=fanout)
         assert ctx.status() == gq.GQ_OK
         k = int(cnt.item())
         assert k == len(ep)
@@ -236,10 +245,22 @@ def test_join_probe_partitioned(ctx, m, n, order):
     h = len(sel) // 2
     n_dev = torch.tensor([h], dtype=torch.int64, device="cuda")
     ep, ey = oracle.join(bkey, bpay, fk, sel[:h])
-    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=dev(sel), n_dev=n_dev)
+    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, dev(fk), sel=dev(sel), n_dev=n_dev,
+                                                  log2_fanout=fanout)
     k = int(cnt.item())
     assert k == len(ep)
     assert np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
+
+
+def test_join_probe_partitioned_table_size_checked(ctx):
+    """A table size that does not match the table's header is reported."""
+    bkey, bpay = _dim(2_000_000, 11)
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay))
+    fk = dev(bkey[:100_000])
+    gq.gq_join_probe_partitioned(ctx, table[:table.numel() - 4096], fk, log2_fanout=6)
+    assert ctx.status() == gq.GQ_ERR_INVALID_ARG
+    prow, pay, cnt = gq.gq_join_probe_partitioned(ctx, table, fk, log2_fanout=6)
+    assert ctx.status() == gq.GQ_OK and int(cnt.item()) == 100_000
 
 
 def test_join_probe_partitioned_empty(ctx):
