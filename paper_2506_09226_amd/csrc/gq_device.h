@@ -136,18 +136,32 @@ GQ_DEV void gq_atomic_store64(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Publishing and waiting, separately: a tile can publish its aggregate as
+// soon as it is known and wait for its predecessors later.  Both are called
+// by all 64 lanes of ONE wave, publish first.
+GQ_DEV void gq_lookback_publish(uint64_t *status, uint32_t t, uint64_t agg)
+{
+    if (gq_lane() == 0) gq_atomic_store64(&status[t], (t == 0 ? GQ_LB_INC : GQ_LB_AGG) | agg);
+}
+
+GQ_DEV uint64_t gq_lookback_wait(uint64_t *status, uint32_t t, uint64_t agg);
+
 // Called by all 64 lanes of ONE wave.  Publishes `agg` for tile `t`, waits for
 // the predecessors and returns the exclusive prefix of tile t (same value in
 // every lane).  Tiles are taken in increasing order from an atomic counter,
 // so every predecessor belongs to a running or finished workgroup.
 GQ_DEV uint64_t gq_lookback(uint64_t *status, uint32_t t, uint64_t agg)
 {
+    gq_lookback_publish(status, t, agg);
+    return gq_lookback_wait(status, t, agg);
+}
+
+// The waiting half: the exclusive prefix of tile t, whose aggregate `agg`
+// was published; then publishes t's inclusive value.
+GQ_DEV uint64_t gq_lookback_wait(uint64_t *status, uint32_t t, uint64_t agg)
+{
     const int lane = gq_lane();
-    if (t == 0) {
-        if (lane == 0) gq_atomic_store64(&status[0], GQ_LB_INC | agg);
-        return 0;
-    }
-    if (lane == 0) gq_atomic_store64(&status[t], GQ_LB_AGG | agg);
+    if (t == 0) return 0;
     uint64_t excl = 0;
     int64_t top = static_cast<int64_t>(t) - 1;        // window = [top-63, top]
     while (true) {

@@ -825,7 +825,11 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
 // bitmap, scattered by the stored in-tile index), then the ordered compaction
 // of the matches (block scan + decoupled look-back).  Only the in-tile index
 // of each match is staged; its row id is read from the selection as it is
-// written out.  About 25 KB of LDS, so six workgroups share a CU.
+// written out.  Persistent: a workgroup takes tiles in increasing order from
+// a counter and issues the loads of its next tile before it compacts the
+// current one; its barriers order LDS only, so those loads stay in flight.
+// Look-back cannot deadlock: the smallest unfinished tile is always some
+// workgroup's current tile, and it waits only on smaller tiles.
 template <bool HAS_SEL>
 __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t n_bound, const int64_t *n_dev,
                                                                 const int32_t *__restrict__ sel,
@@ -836,72 +840,106 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
     __shared__ uint16_t stage_i[JX_TILE];                 // in-tile index of each staged match
     __shared__ uint32_t hitw[JX_TILE / 32];               // hit bitmap in probe order
     __shared__ uint32_t scan_smem[JX_THREADS / 64];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_next;
     __shared__ uint64_t s_goff;
     const int64_t n = jx_eff_n(n_bound, n_dev);
-    if (threadIdx.x == 0) s_tile = atomicAdd(&w.ctr[32], 1u);
-    if (threadIdx.x < JX_TILE / 32) hitw[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t t = s_tile;
     const int64_t ntiles = (n + JX_TILE - 1) / JX_TILE;
-    if (static_cast<int64_t>(t) >= ntiles) {
-        if (t == 0 && threadIdx.x == 0) *n_out = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (ntiles == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = 0;
         return;
     }
-    const int64_t base = static_cast<int64_t>(t) * JX_TILE;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t rows = n - base < JX_TILE ? n - base : JX_TILE;
+    auto load_tile = [&](int64_t t, uint16_t *ix, int64_t *rv) {
+#pragma unroll
+        for (int c = 0; c < JX_ITEMS; ++c) {
+            const int64_t p = t * JX_TILE + c * JX_THREADS + threadIdx.x;     // pool position
+            ix[c] = 0;
+            rv[c] = -1;
+            if (t < ntiles && p < n) {
+                ix[c] = static_cast<uint16_t>(w.sidx[p] & (JX_TILE - 1));
+                rv[c] = w.res[p];
+            }
+        }
+    };
+    if (threadIdx.x == 0) s_next = atomicAdd(&w.ctr[32], 1u);
+    __syncthreads();
+    int64_t t = static_cast<int64_t>(gq_uniform(s_next));
     uint16_t ix[JX_ITEMS];
     int64_t rv[JX_ITEMS];
+    load_tile(t, ix, rv);
+    while (t < ntiles) {
+        const int64_t base = t * JX_TILE;
+        uint32_t nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(&w.ctr[32], 1u);  // the next tile, dequeued early
+        if (threadIdx.x < JX_TILE / 32) hitw[threadIdx.x] = 0;
+        // every thread has read s_next (the current tile) and finished the
+        // last tile's LDS reads; hitw is clear
+        gq_lds_barrier();
+        if (threadIdx.x == 0) s_next = nxt;
 #pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t p = base + c * JX_THREADS + threadIdx.x;     // pool position
-        ix[c] = 0;
-        rv[c] = -1;
-        if (p < n) {
-            ix[c] = static_cast<uint16_t>(w.sidx[p] & (JX_TILE - 1));
-            rv[c] = w.res[p];
+        for (int c = 0; c < JX_ITEMS; ++c) {
+            const int64_t p = base + c * JX_THREADS + threadIdx.x;
+            if (p < n) {
+                pay[ix[c]] = static_cast<int32_t>(rv[c]);
+                if (rv[c] >= 0) atomicOr(&hitw[ix[c] >> 5], 1u << (ix[c] & 31));
+            }
         }
-    }
-#pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
-        const int64_t p = base + c * JX_THREADS + threadIdx.x;
-        if (p < n) {
-            pay[ix[c]] = static_cast<int32_t>(rv[c]);
-            if (rv[c] >= 0) atomicOr(&hitw[ix[c] >> 5], 1u << (ix[c] & 31));
+        const int64_t tn = static_cast<int64_t>(gq_uniform(s_next));
+        gq_lds_barrier();
+        load_tile(tn, ix, rv);                             // next tile: in flight meanwhile
+        if (wave == 0) {                                   // the tile's match count, published at once
+            const uint32_t c = __popc(hitw[lane]) + __popc(hitw[lane + 64]);
+            gq_lookback_publish(w.status, static_cast<uint32_t>(t), gq_wave_sum(c));
         }
-    }
-    __syncthreads();
-    // thread i owns probe-order elements [16 i, 16 i + 16)
-    const int elem0 = threadIdx.x * JX_ITEMS;
-    uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & 0xffffu;
-    if (elem0 + JX_ITEMS > rows) mine &= rows > elem0 ? (1u << (rows - elem0)) - 1 : 0u;
-    int32_t my_pay[JX_ITEMS];
+        // thread i owns probe-order elements [16 i, 16 i + 16)
+        const int elem0 = threadIdx.x * JX_ITEMS;
+        const uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & 0xffffu;
+        int32_t my_pay[JX_ITEMS];
 #pragma unroll
-    for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[elem0 + i];
-    uint32_t total;
-    uint32_t pos = gq_block_exclusive_scan<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
-    if (wave == 0) {
-        const uint64_t g = gq_lookback(w.status, t, total);
-        if (lane == 0) s_goff = g;
-    }
-    // the scan's barriers ordered every read of pay[] before these writes
-#pragma unroll
-    for (int i = 0; i < JX_ITEMS; ++i) {
-        if (mine & (1u << i)) {
-            stage_i[pos] = static_cast<uint16_t>(elem0 + i);
-            pay[pos] = my_pay[i];
-            ++pos;
+        for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[elem0 + i];
+        uint32_t total;
+        uint32_t pos = gq_block_exclusive_scan_lds<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+        if (wave == 0) {
+            const uint64_t g = gq_lookback_wait(w.status, static_cast<uint32_t>(t), total);
+            if (lane == 0) s_goff = g;
         }
+        // the scan's barriers ordered every read of pay[] before these writes
+#pragma unroll
+        for (int i = 0; i < JX_ITEMS; ++i) {
+            if (mine & (1u << i)) {
+                stage_i[pos] = static_cast<uint16_t>(elem0 + i);
+                pay[pos] = my_pay[i];
+                ++pos;
+            }
+        }
+        gq_lds_barrier();
+        const int64_t goff = static_cast<int64_t>(s_goff);
+        const uint32_t tot = static_cast<uint32_t>(gq_uniform(total));
+        for (uint32_t i0 = 0; i0 < tot; i0 += JX_THREADS * 4) {
+            int32_t rw[4], py[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t i = i0 + c * JX_THREADS + threadIdx.x;
+                rw[c] = 0;
+                py[c] = 0;
+                if (i < tot) {
+                    const int64_t e = base + stage_i[i];
+                    rw[c] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
+                    py[c] = pay[i];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t i = i0 + c * JX_THREADS + threadIdx.x;
+                if (i < tot) {
+                    prow_out[goff + i] = rw[c];
+                    pay_out[goff + i] = py[c];
+                }
+            }
+        }
+        if (t == ntiles - 1 && threadIdx.x == 0) *n_out = goff + tot;
+        t = tn;
     }
-    __syncthreads();
-    const int64_t goff = static_cast<int64_t>(s_goff);
-    for (uint32_t i = threadIdx.x; i < total; i += JX_THREADS) {
-        const int64_t e = base + stage_i[i];
-        prow_out[goff + i] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
-        pay_out[goff + i] = pay[i];
-    }
-    if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
 }
 
 }  // namespace
@@ -1043,10 +1081,12 @@ gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table
     const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(want, gm.nregions));
     GQ_TRY(gq_launch(ctx, "gq_join_probe_regions", jx_region_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, gm,
                      w));
+    // persistent compaction: four workgroups per CU (122 VGPRs)
+    const uint32_t cgrid = static_cast<uint32_t>(std::min<int64_t>(w.ntiles, static_cast<int64_t>(ctx->num_cus) * 4));
     if (sel)
-        return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s,
+        return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true>, dim3(cgrid), dim3(JX_THREADS), 0, s,
                          w, n, n_dev, sel, prow_out, payload_out, n_out_dev);
-    return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s, w,
+    return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<false>, dim3(cgrid), dim3(JX_THREADS), 0, s, w,
                      n, n_dev, sel, prow_out, payload_out, n_out_dev);
 }
 }  // extern "C"
