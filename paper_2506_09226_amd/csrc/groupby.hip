@@ -520,7 +520,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
 #pragma unroll 4
         for (int c = 0; c < ITEMS; ++c) {
             const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            if (j < c1 && row_pass(a, value_row(a, j))) {
+            if (j < c1 && (!a.filter || row_pass(a, value_row(a, j)))) {   // row id read only to filter
                 int64_t k64;
                 int32_t k32;
                 load_key<K64, K32>(a, j, k64, k32);
@@ -532,10 +532,15 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
     for (int b = threadIdx.x; b < P; b += GB_THREADS) hist[static_cast<int64_t>(blockIdx.x) * P + b] = h[b];
 }
 
-// Scatter one tile: rank each row inside its bucket with an LDS atomic (the
-// order inside a bucket does not matter to sums), stage the records in LDS in
-// bucket order, then write them out as contiguous runs starting at the
-// tile's offset gofs[t * P + b] in each bucket.
+// Scatter of 2048-row tiles: rank each row inside its bucket with an LDS
+// atomic (the order inside a bucket does not matter to sums), stage the
+// records in LDS in bucket order, then write them out as contiguous runs
+// starting at the tile's offset gofs[t * P + b] in each bucket.
+// Persistent: XCD x (workgroups b with b mod 8 = x) takes one contiguous
+// eighth of the tiles, its workgroups interleaved over it, so a bucket's runs
+// from neighbouring tiles meet in one L2.  The row ids, directly indexed keys
+// and bucket offsets of a workgroup's next tile are loaded while it scatters
+// the current one; the barriers order LDS only, so those loads stay in flight.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P, const uint32_t *__restrict__ gofs,
                                                                 uint64_t *__restrict__ recs,
@@ -544,85 +549,130 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
     constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
     constexpr int TILE = gb_fmt<K64, K32>::TILE;
     constexpr int W = gb_fmt<K64, K32>::WORDS;
+    constexpr int GPER = GB_MAX_P / GB_THREADS;
     __shared__ uint32_t lpos[GB_MAX_P];          // counts -> local starts -> (global - local) starts
     __shared__ uint32_t scan_smem[GB_THREADS / 64];
     __shared__ uint16_t lbucket[TILE];
     __shared__ uint64_t stage[TILE * W];
-    const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
     const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t base = static_cast<int64_t>(tile) * TILE;
-    if (base >= n) return;                          // whole block: uniform
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = 0;
-    // this tile's bucket offsets, loaded now so they arrive with the rows
-    constexpr int GPER = GB_MAX_P / GB_THREADS;
+    const int64_t nt = (n + TILE - 1) / TILE;
+    const uint32_t G = gridDim.x, xcd = blockIdx.x % GQ_NUM_XCD, jw = blockIdx.x / GQ_NUM_XCD;
+    const uint32_t J = G / GQ_NUM_XCD + (xcd < G % GQ_NUM_XCD ? 1u : 0u);
+    const int64_t r1 = nt * (xcd + 1) / GQ_NUM_XCD;
+    auto prefetch = [&](int64_t t, int32_t *pv, int64_t *pk64, int32_t *pk32, uint32_t *pgo) {
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            const int64_t j = t * TILE + c * GB_THREADS + threadIdx.x;
+            pv[c] = 0;
+            pk64[c] = 0;
+            pk32[c] = 0;
+            if (t < r1 && j < n) {
+                pv[c] = a.rowid ? a.rowid[j] : static_cast<int32_t>(j);
+                if (K64 && !a.key64_by_rowid) pk64[c] = a.key64[j];
+                if (K32 && !a.key32_by_rowid) pk32[c] = a.key32[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < GPER; ++i) {
+            const int b = threadIdx.x + i * GB_THREADS;
+            pgo[i] = (t < r1 && b < P) ? gofs[t * P + b] : 0u;
+        }
+    };
+    int64_t t = nt * xcd / GQ_NUM_XCD + jw;
+    int32_t v[ITEMS];
+    int64_t k64[ITEMS];
+    int32_t k32[ITEMS];
     uint32_t go[GPER];
+    prefetch(t, v, k64, k32, go);
+    for (; t < r1; t += J) {
+        const int64_t base = t * TILE;
+        gq_lds_barrier();                               // the last tile's LDS reads are done
+        for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = 0;
+        int64_t qv[ITEMS], pv[ITEMS], dv[ITEMS];
+        bool keep[ITEMS];
 #pragma unroll
-    for (int i = 0; i < GPER; ++i) {
-        const int b = threadIdx.x + i * GB_THREADS;
-        go[i] = b < P ? gofs[static_cast<int64_t>(tile) * P + b] : 0u;
-    }
-    __syncthreads();
-    uint64_t w[ITEMS][W];
-    uint32_t pos[ITEMS];
-    bool keep[ITEMS];
-#pragma unroll
-    for (int c = 0; c < ITEMS; ++c) {
-        const int64_t j = base + c * GB_THREADS + threadIdx.x;
-        const int64_t v = j < n ? value_row(a, j) : 0;
-        keep[c] = j < n && row_pass(a, v);
-        if (keep[c]) {
-            const int64_t k64 = K64 ? a.key64[a.key64_by_rowid ? v : j] : 0;
-            const int32_t k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
-            const int64_t qty = a.qty[v];
-            const gq_i128 rev = gq_revenue(a.price[v], a.rev_scale, a.disc[v]);
-            const bool nar = is_narrow(qty, rev);
-            if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
-            make_words<K64, K32>(w[c], k64, k32, nar ? static_cast<int32_t>(qty) : 0,
-                                 nar ? static_cast<int64_t>(rev.lo) : 0);
-            const uint32_t b = gb_bucket(gb_hash(k64, k32), P);
-            pos[c] = (b << 16) | atomicAdd(&lpos[b], 1u);
+        for (int c = 0; c < ITEMS; ++c) {               // this tile's value gathers
+            const int64_t j = base + c * GB_THREADS + threadIdx.x;
+            keep[c] = j < n && (!a.filter || row_pass(a, v[c]));
+            qv[c] = pv[c] = dv[c] = 0;
+            if (keep[c]) {
+                if (K64 && a.key64_by_rowid) k64[c] = a.key64[v[c]];
+                if (K32 && a.key32_by_rowid) k32[c] = a.key32[v[c]];
+                qv[c] = a.qty[v[c]];
+                pv[c] = a.price[v[c]];
+                dv[c] = a.disc[v[c]];
+            }
         }
-    }
-    __syncthreads();
-    const int per = (P + GB_THREADS - 1) / GB_THREADS;
-    uint32_t local = 0;
-    for (int i = 0; i < per; ++i) {
-        const int b = threadIdx.x * per + i;
-        if (b < P) local += lpos[b];
-    }
-    uint32_t all;
-    uint32_t run = gq_block_exclusive_scan<GB_THREADS>(local, &all, scan_smem);
-    for (int i = 0; i < per; ++i) {
-        const int b = threadIdx.x * per + i;
-        if (b < P) {
-            const uint32_t c = lpos[b];
-            lpos[b] = run;
-            run += c;
+        int32_t nv[ITEMS];
+        int64_t nk64[ITEMS];
+        int32_t nk32[ITEMS];
+        uint32_t ngo[GPER];
+        prefetch(t + J, nv, nk64, nk32, ngo);           // the next tile: in flight meanwhile
+        gq_lds_barrier();                               // lpos cleared
+        uint64_t w[ITEMS][W];
+        uint32_t pos[ITEMS];
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            if (keep[c]) {
+                const int64_t j = base + c * GB_THREADS + threadIdx.x;
+                const gq_i128 rev = gq_revenue(pv[c], a.rev_scale, dv[c]);
+                const bool nar = is_narrow(qv[c], rev);
+                if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
+                make_words<K64, K32>(w[c], k64[c], k32[c], nar ? static_cast<int32_t>(qv[c]) : 0,
+                                     nar ? static_cast<int64_t>(rev.lo) : 0);
+                const uint32_t b = gb_bucket(gb_hash(k64[c], k32[c]), P);
+                pos[c] = (b << 16) | atomicAdd(&lpos[b], 1u);
+            }
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < ITEMS; ++c) {
-        if (keep[c]) {
-            const uint32_t b = pos[c] >> 16;
-            const uint32_t q = lpos[b] + (pos[c] & 0xffffu);
-            lbucket[q] = static_cast<uint16_t>(b);
-#pragma unroll
-            for (int x = 0; x < W; ++x) stage[q * W + x] = w[c][x];
+        gq_lds_barrier();
+        const int per = (P + GB_THREADS - 1) / GB_THREADS;
+        uint32_t local = 0;
+        for (int i = 0; i < per; ++i) {
+            const int b = threadIdx.x * per + i;
+            if (b < P) local += lpos[b];
         }
-    }
-    __syncthreads();
+        uint32_t all;
+        uint32_t run = gq_block_exclusive_scan_lds<GB_THREADS>(local, &all, scan_smem);
+        for (int i = 0; i < per; ++i) {
+            const int b = threadIdx.x * per + i;
+            if (b < P) {
+                const uint32_t c = lpos[b];
+                lpos[b] = run;
+                run += c;
+            }
+        }
+        gq_lds_barrier();
 #pragma unroll
-    for (int i = 0; i < GPER; ++i) {
-        const int b = threadIdx.x + i * GB_THREADS;
-        if (b < P) lpos[b] = go[i] - lpos[b];
-    }
-    __syncthreads();
-    const uint32_t words = all * W;                  // rows of this tile that pass the filter
-    for (uint32_t e = threadIdx.x; e < words; e += GB_THREADS) {
-        const uint32_t q = e / W, x = e - q * W;
-        const uint32_t row = q + lpos[lbucket[q]];  // global row position in the bucket array
-        recs[static_cast<int64_t>(row) * W + x] = stage[e];
+        for (int c = 0; c < ITEMS; ++c) {
+            if (keep[c]) {
+                const uint32_t b = pos[c] >> 16;
+                const uint32_t q = lpos[b] + (pos[c] & 0xffffu);
+                lbucket[q] = static_cast<uint16_t>(b);
+#pragma unroll
+                for (int x = 0; x < W; ++x) stage[q * W + x] = w[c][x];
+            }
+        }
+        gq_lds_barrier();
+#pragma unroll
+        for (int i = 0; i < GPER; ++i) {
+            const int b = threadIdx.x + i * GB_THREADS;
+            if (b < P) lpos[b] = go[i] - lpos[b];
+        }
+        gq_lds_barrier();
+        const uint32_t words = all * W;                  // rows of this tile that pass the filter
+        for (uint32_t e = threadIdx.x; e < words; e += GB_THREADS) {
+            const uint32_t q = e / W, x = e - q * W;
+            const uint32_t row = q + lpos[lbucket[q]];  // global row position in the bucket array
+            recs[static_cast<int64_t>(row) * W + x] = stage[e];
+        }
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            v[c] = nv[c];
+            k64[c] = nk64[c];
+            k32[c] = nk32[c];
+        }
+#pragma unroll
+        for (int i = 0; i < GPER; ++i) go[i] = ngo[i];
     }
 }
 
@@ -887,7 +937,8 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                          s, a, pl.P, pl.chunk_rows, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
                          w.side_cnt));
     else
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0, s,
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>,
+                         dim3(static_cast<uint32_t>(std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3)))), dim3(GB_THREADS), 0, s,
                          a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt));
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
