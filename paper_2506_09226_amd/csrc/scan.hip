@@ -85,6 +85,10 @@ constexpr int TO_THREADS = 256;
 constexpr int TO_MAX_P = 8192;
 constexpr int TO_START_THREADS = 1024;
 
+// Column loops load TO_BATCH counts into registers before using them, so a
+// thread keeps that many independent loads in flight.
+constexpr int TO_BATCH = 32;
+
 __global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
                                                                   int P, uint32_t *__restrict__ csum)
 {
@@ -94,8 +98,13 @@ __global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t
     const int64_t t0 = c * TO_CHUNK;
     const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
     uint32_t s = 0;
-#pragma unroll 8
-    for (int64_t t = t0; t < t1; ++t) s += cnt[t * P + b];
+    for (int64_t t = t0; t < t1; t += TO_BATCH) {
+        uint32_t x[TO_BATCH];
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) x[i] = t + i < t1 ? cnt[(t + i) * P + b] : 0u;
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) s += x[i];
+    }
     csum[c * P + b] = s;
 }
 
@@ -105,11 +114,15 @@ __global__ __launch_bounds__(TO_THREADS) void to_chunk_scan_kernel(uint32_t *__r
     const int b = blockIdx.x * TO_THREADS + threadIdx.x;
     if (b >= P) return;
     uint32_t run = 0;
-#pragma unroll 8
-    for (int64_t c = 0; c < nchunks; ++c) {
-        const uint32_t x = csum[c * P + b];
-        csum[c * P + b] = run;
-        run += x;
+    for (int64_t c = 0; c < nchunks; c += TO_BATCH) {
+        uint32_t x[TO_BATCH];
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) x[i] = c + i < nchunks ? csum[(c + i) * P + b] : 0u;
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) {
+            if (c + i < nchunks) csum[(c + i) * P + b] = run;
+            run += x[i];
+        }
     }
     total[b] = run;
 }
@@ -145,11 +158,15 @@ __global__ __launch_bounds__(TO_THREADS) void to_final_kernel(uint32_t *__restri
     const int64_t t0 = c * TO_CHUNK;
     const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
     uint32_t run = start[b] + csum[c * P + b];
-#pragma unroll 8
-    for (int64_t t = t0; t < t1; ++t) {
-        const uint32_t x = cnt[t * P + b];
-        cnt[t * P + b] = run;
-        run += x;
+    for (int64_t t = t0; t < t1; t += TO_BATCH) {
+        uint32_t x[TO_BATCH];
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) x[i] = t + i < t1 ? cnt[(t + i) * P + b] : 0u;
+#pragma unroll
+        for (int i = 0; i < TO_BATCH; ++i) {
+            if (t + i < t1) cnt[(t + i) * P + b] = run;
+            run += x[i];
+        }
     }
 }
 
