@@ -537,28 +537,30 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
 // records in LDS in bucket order, then write them out as contiguous runs
 // starting at the tile's offset gofs[t * P + b] in each bucket.
 // Persistent: XCD x (workgroups b with b mod 8 = x) takes one contiguous
-// eighth of the tiles, its workgroups interleaved over it, so a bucket's runs
-// from neighbouring tiles meet in one L2.  The row ids, directly indexed keys
-// and bucket offsets of a workgroup's next tile are loaded while it scatters
-// the current one; the barriers order LDS only, so those loads stay in flight.
+// eighth of the tiles, in order, from its own counter (xctr[x]), so a
+// bucket's runs from neighbouring tiles reach one L2 close together in time
+// and leave it as whole lines.  The row ids, directly indexed keys and bucket
+// offsets of a workgroup's next tile are loaded while it scatters the current
+// one; the barriers order LDS only, so those loads stay in flight.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P, const uint32_t *__restrict__ gofs,
                                                                 uint64_t *__restrict__ recs,
-                                                                uint32_t *__restrict__ side, uint32_t *side_cnt)
+                                                                uint32_t *__restrict__ side, uint32_t *side_cnt,
+                                                                uint32_t *xctr)
 {
     constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
     constexpr int TILE = gb_fmt<K64, K32>::TILE;
     constexpr int W = gb_fmt<K64, K32>::WORDS;
     constexpr int GPER = GB_MAX_P / GB_THREADS;
+    __shared__ uint32_t s_next;
     __shared__ uint32_t lpos[GB_MAX_P];          // counts -> local starts -> (global - local) starts
     __shared__ uint32_t scan_smem[GB_THREADS / 64];
     __shared__ uint16_t lbucket[TILE];
     __shared__ uint64_t stage[TILE * W];
     const int64_t n = eff_n(a.n_bound, a.n_dev);
     const int64_t nt = (n + TILE - 1) / TILE;
-    const uint32_t G = gridDim.x, xcd = blockIdx.x % GQ_NUM_XCD, jw = blockIdx.x / GQ_NUM_XCD;
-    const uint32_t J = G / GQ_NUM_XCD + (xcd < G % GQ_NUM_XCD ? 1u : 0u);
-    const int64_t r1 = nt * (xcd + 1) / GQ_NUM_XCD;
+    const uint32_t xcd = blockIdx.x % GQ_NUM_XCD;
+    const int64_t r0 = nt * xcd / GQ_NUM_XCD, r1 = nt * (xcd + 1) / GQ_NUM_XCD;
     auto prefetch = [&](int64_t t, int32_t *pv, int64_t *pk64, int32_t *pk32, uint32_t *pgo) {
 #pragma unroll
         for (int c = 0; c < ITEMS; ++c) {
@@ -578,15 +580,22 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
             pgo[i] = (t < r1 && b < P) ? gofs[t * P + b] : 0u;
         }
     };
-    int64_t t = nt * xcd / GQ_NUM_XCD + jw;
+    if (threadIdx.x == 0) s_next = atomicAdd(&xctr[xcd], 1u);
+    __syncthreads();
+    int64_t t = r0 + static_cast<int64_t>(gq_uniform(s_next));
     int32_t v[ITEMS];
     int64_t k64[ITEMS];
     int32_t k32[ITEMS];
     uint32_t go[GPER];
     prefetch(t, v, k64, k32, go);
-    for (; t < r1; t += J) {
+    while (t < r1) {
         const int64_t base = t * TILE;
-        gq_lds_barrier();                               // the last tile's LDS reads are done
+        uint32_t nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(&xctr[xcd], 1u);   // the next tile, dequeued early
+        // every thread has read s_next (the current tile) and finished the
+        // last tile's LDS reads
+        gq_lds_barrier();
+        if (threadIdx.x == 0) s_next = nxt;
         for (int b = threadIdx.x; b < P; b += GB_THREADS) lpos[b] = 0;
         int64_t qv[ITEMS], pv[ITEMS], dv[ITEMS];
         bool keep[ITEMS];
@@ -607,8 +616,9 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
         int64_t nk64[ITEMS];
         int32_t nk32[ITEMS];
         uint32_t ngo[GPER];
-        prefetch(t + J, nv, nk64, nk32, ngo);           // the next tile: in flight meanwhile
-        gq_lds_barrier();                               // lpos cleared
+        gq_lds_barrier();                               // lpos cleared; s_next set
+        const int64_t tn = r0 + static_cast<int64_t>(gq_uniform(s_next));
+        prefetch(tn, nv, nk64, nk32, ngo);              // the next tile: in flight meanwhile
         uint64_t w[ITEMS][W];
         uint32_t pos[ITEMS];
 #pragma unroll
@@ -673,6 +683,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
         }
 #pragma unroll
         for (int i = 0; i < GPER; ++i) go[i] = ngo[i];
+        t = tn;
     }
 }
 
@@ -895,7 +906,7 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     w.g.lo = c.take<uint64_t>(S);
     w.g.hi = c.take<int64_t>(S);
     w.g.mask = S - 1;
-    w.side_cnt = c.take<uint32_t>(64);
+    w.side_cnt = c.take<uint32_t>(64);      // [0] wide rows; [16..23] scatter tile counters per XCD
     w.zero_bytes = c.off;
     if (!pl.small) {
         const size_t rows = static_cast<size_t>(n > 0 ? n : 1);
@@ -939,7 +950,8 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
     else
         GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>,
                          dim3(static_cast<uint32_t>(std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3)))), dim3(GB_THREADS), 0, s,
-                         a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt));
+                         a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt,
+                         w.side_cnt + 16));
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));
