@@ -589,6 +589,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
     uint32_t go[GPER];
     prefetch(t, v, k64, k32, go);
     while (t < r1) {
+        gq_lds_barrier();                               // opens each pass (thread-0 work never merges across passes)
         const int64_t base = t * TILE;
         uint32_t nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(&xctr[xcd], 1u);   // the next tile, dequeued early

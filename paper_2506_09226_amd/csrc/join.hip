@@ -868,6 +868,9 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
     int64_t rv[JX_ITEMS];
     load_tile(t, ix, rv);
     while (t < ntiles) {
+        // a barrier opens each pass, so thread-0 work of consecutive passes
+        // (the count store below, the dequeue here) is never merged
+        gq_lds_barrier();
         const int64_t base = t * JX_TILE;
         uint32_t nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(&w.ctr[32], 1u);  // the next tile, dequeued early
