@@ -185,13 +185,15 @@ def test_skewed_workload_full_size_sampled(ctx):
     assert int(g["count"].sum()) == nj
 
 
-def test_one_gpu_share_full_size_sampled(ctx):
+@pytest.mark.parametrize("probe", ["partitioned", "ordered"])
+def test_one_gpu_share_full_size_sampled(ctx, probe):
     """200M fact rows, 25M dim rows, 64 buckets, ~1.5M groups: the benchmark's
-    launch configuration, checked on sampled outputs and invariants."""
+    launch configuration (partitioned probe) and the ordered probe, checked on
+    sampled outputs and invariants."""
     w = synth.workload(1)
     fact, dim = _tables(w, "cuda")
     n, m = w.fact.n, w.dim_m
-    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=6, topk=100)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=6, topk=100, probe=probe)
     pl.step()
     torch.cuda.synchronize()
     assert ctx.status() == gq.GQ_OK
