@@ -469,16 +469,19 @@ def test_groupby_large_path_wide_rows(ctx, composite, overflow):
     _check_groups(res, exp, composite, True)
 
 
+@pytest.mark.parametrize("qlo", [-(1 << 31), 0])
 @pytest.mark.parametrize("groups", [25, 5000, 150_000])
-def test_groupby_signed_revenues_in_narrow_records(ctx, groups):
-    """Revenues that fit 64 bits but not 32, of both signs, and negative
-    quantities: every row stays a narrow record, the split low/high revenue
-    sums carry nonzero (negative) high halves, and group totals pass 2^64."""
+def test_groupby_signed_revenues_in_narrow_records(ctx, groups, qlo):
+    """Revenues that fit 64 bits but not 32, of both signs, and quantities
+    over all of int32 (or all non-negative int32, too wide to share a word
+    with the count): every row stays a narrow record, the split low/high
+    revenue sums carry nonzero (negative) high halves, and group totals pass
+    2^64."""
     r = rng(88 + groups)
     n = nv = 300_000
     key32 = r.integers(0, groups, size=n).astype(np.int32)
     rowid = r.integers(0, nv, size=n).astype(np.int32)
-    qty = r.integers(-(1 << 31), 1 << 31, size=nv).astype(np.int64)
+    qty = r.integers(qlo, 1 << 31, size=nv).astype(np.int64)
     price = r.integers(1, 1 << 55, size=nv, dtype=np.int64) * np.where(r.random(nv) < 0.4, -1, 1)
     disc = r.integers(-20, 11, size=nv).astype(np.int64)
     exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
