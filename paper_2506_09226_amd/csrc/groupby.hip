@@ -274,8 +274,13 @@ GQ_DEV int64_t g_find(const gtable &g, bool active, uint64_t h, int64_t k64, int
         if (!done) {
             const uint32_t st = atomicCAS(&g.state[s], 0u, 1u);
             if (st == 0u) {
+                // the claimer zeroes the sums: only the state words start cleared
                 if (K64) __hip_atomic_store(&g.k64[s], k64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (K32) __hip_atomic_store(&g.k32[s], k32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&g.cnt[s], uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&g.sq[s], uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&g.lo[s], uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&g.hi[s], int64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&g.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 found = static_cast<int64_t>(s);
                 done = true;
@@ -398,25 +403,38 @@ __global__ __launch_bounds__(GB_THREADS) void gb_small_kernel(gb_args a, gtable 
     }
 }
 
-// Compact the occupied slots of a global table into the output.
+// Compact the occupied (state 2) slots of a global table into the output.
+// Workgroup w owns one contiguous range of slots: it counts them, takes its
+// output range with one atomic on the group counter (many atomics on one
+// address serialize), then writes its groups in slot order.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups out, uint32_t *status)
 {
+    __shared__ uint32_t scan_smem[256 / 64];
+    __shared__ unsigned long long s_base;
     const uint64_t slots = g.mask + 1;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t b = static_cast<uint64_t>(blockIdx.x) * blockDim.x; b < slots; b += stride) {
+    const uint64_t per = (slots + gridDim.x - 1) / gridDim.x;
+    const uint64_t s0 = static_cast<uint64_t>(blockIdx.x) * per;
+    const uint64_t s1 = s0 + per < slots ? s0 + per : slots;
+    uint32_t mine = 0;
+    for (uint64_t s = s0 + threadIdx.x; s < s1; s += 256) mine += g.state[s] == 2u ? 1u : 0u;
+    uint32_t total;
+    (void)gq_block_exclusive_scan<256>(mine, &total, scan_smem);
+    if (total == 0) return;                          // same value for the whole workgroup
+    if (threadIdx.x == 0)
+        s_base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_groups),
+                           static_cast<unsigned long long>(total));
+    __syncthreads();
+    int64_t idx = static_cast<int64_t>(s_base);
+    for (uint64_t b = s0; b < s1; b += 256) {
         const uint64_t s = b + threadIdx.x;
-        const bool occ = s < slots && g.state[s] == 2u;
-        const uint64_t m = gq_ballot(occ);
-        if (!m) continue;
-        unsigned long long basei = 0;
-        if (gq_lane() == 0)
-            basei = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_groups),
-                              static_cast<unsigned long long>(__popcll(m)));
-        basei = __shfl(basei, 0, 64);
+        const bool occ = s < s1 && g.state[s] == 2u;
+        uint32_t step;
+        const uint32_t pre = gq_block_exclusive_scan<256>(occ ? 1u : 0u, &step, scan_smem);
         if (occ)
-            emit_group(out, static_cast<int64_t>(basei + gq_mbcnt(m)), K64 ? g.k64[s] : 0, K32 ? g.k32[s] : 0,
-                       g.cnt[s], g.sq[s], g.lo[s], g.hi[s], status);
+            emit_group(out, idx + pre, K64 ? g.k64[s] : 0, K32 ? g.k32[s] : 0, g.cnt[s], g.sq[s], g.lo[s], g.hi[s],
+                       status);
+        idx += step;
     }
 }
 
@@ -721,10 +739,13 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_wide_kernel(gb_args a, 
     constexpr int TILE = gb_fmt<K64, K32>::TILE;
     constexpr int W = gb_fmt<K64, K32>::WORDS;
     __shared__ uint32_t cursor[GB_MAX_P_WIDE];
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) cursor[b] = gofs[static_cast<int64_t>(blockIdx.x) * P + b];
+    // each XCD takes one contiguous range of chunks, so the runs that
+    // neighbouring chunks append to a bucket meet in one L2
+    const uint32_t chunk = gq_xcd_tile(blockIdx.x, gridDim.x);
+    for (int b = threadIdx.x; b < P; b += GB_THREADS) cursor[b] = gofs[static_cast<int64_t>(chunk) * P + b];
     __syncthreads();
     const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk_rows;
+    const int64_t c0 = static_cast<int64_t>(chunk) * chunk_rows;
     const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
     for (int64_t base = c0; base < c1; base += TILE) {
 #pragma unroll 4
@@ -754,18 +775,82 @@ struct bucket_slots {
     static constexpr int value = K64 ? 3072 : 4096;
 };
 
+// Sums of several rows into slot s (the split form of lds_add_split).
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV void lds_add_sums(lds_table<SLOTS, K64, K32> &T, int s, uint32_t cnt, uint64_t qty, uint64_t lo_sum,
+                         int64_t hi_sum)
+{
+    atomicAdd(&T.cnt[s], cnt);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[s]), static_cast<unsigned long long>(qty));
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[s]), static_cast<unsigned long long>(lo_sum));
+    if (hi_sum) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[s]), static_cast<unsigned long long>(hi_sum));
+}
+
+// Chunks of the bucket pass.  A bucket of at most chunk_rows rows is one
+// chunk; a larger one (a bucket holding a heavy key) is cut into
+// ceil(rows / chunk_rows) chunks, each aggregated by its own workgroup.
+// cstart[b] = number of chunks before bucket b (one workgroup of
+// GB_BUCKET_THREADS threads; P <= GB_MAX_P_WIDE).
+__global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint32_t *__restrict__ start, int P,
+                                                                      int64_t chunk_rows, uint32_t *__restrict__ cstart)
+{
+    __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
+    constexpr int PER = GB_MAX_P_WIDE / GB_BUCKET_THREADS;
+    uint32_t nch[PER];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = threadIdx.x * PER + i;
+        nch[i] = 0;
+        if (b < P) {
+            const int64_t rows = static_cast<int64_t>(start[b + 1]) - static_cast<int64_t>(start[b]);
+            nch[i] = rows > chunk_rows ? static_cast<uint32_t>((rows + chunk_rows - 1) / chunk_rows) : 1u;
+        }
+        mine += nch[i];
+    }
+    uint32_t total;
+    uint32_t run = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &total, scan_smem);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = threadIdx.x * PER + i;
+        if (b < P) cstart[b] = run;
+        run += nch[i];
+    }
+    if (threadIdx.x == 0) cstart[P] = total;
+}
+
+// One workgroup per chunk (grid: an upper bound on the chunk count; the
+// surplus workgroups exit).  A workgroup aggregates its rows in an LDS table.
+// A bucket that is one chunk writes its groups out directly; each chunk of a
+// split bucket adds its partial groups to the global table instead (a few
+// device atomics per group and chunk), which the table's emit pass writes out.
+// Lanes of a wave that update the same slot are summed across the wave first
+// and added by one lane, so a heavy key costs one LDS update per wave rather
+// than one per row.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint64_t *__restrict__ recs,
                                                                       const uint32_t *__restrict__ start,
-                                                                      const uint32_t *side_cnt, gtable g,
-                                                                      gq_groups out, uint32_t *status)
+                                                                      const uint32_t *__restrict__ cstart, int P,
+                                                                      int64_t chunk_rows, const uint32_t *side_cnt,
+                                                                      gtable g, gq_groups out, uint32_t *status)
 {
     constexpr int SLOTS = bucket_slots<K64, K32>::value;
     __shared__ lds_table<SLOTS, K64, K32> T;
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     __shared__ unsigned long long s_base;
-    const int b = static_cast<int>(blockIdx.x);
-    const int64_t r0 = start[b], r1 = start[b + 1];
+    const uint32_t ch = blockIdx.x;
+    if (ch >= cstart[P]) return;                     // same value for the whole workgroup
+    int b = 0;                                       // the bucket of chunk ch: last b with cstart[b] <= ch
+    for (int hi = P - 1; b < hi;) {
+        const int mid = (b + hi + 1) >> 1;
+        if (cstart[mid] <= ch) b = mid;
+        else hi = mid - 1;
+    }
+    const uint32_t nch = cstart[b + 1] - cstart[b];
+    const bool split = nch > 1;
+    const int64_t b0 = start[b], b1 = start[b + 1];
+    const int64_t r0 = split ? b0 + static_cast<int64_t>(ch - cstart[b]) * chunk_rows : b0;
+    const int64_t r1 = split ? (r0 + chunk_rows < b1 ? r0 + chunk_rows : b1) : b1;
     lds_init(T);
     __syncthreads();
     constexpr int STEP = GB_BUCKET_THREADS * GB_BUCKET_ITEMS;
@@ -788,11 +873,40 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
             rev.hi = rv[c] >> 63;
             const uint64_t h = gb_hash(k64[c], k32[c]);
             const int s = lds_find(T, active, h, k64[c], k32[c]);
-            if (active && s >= 0) lds_add_split(T, s, q[c], rv[c]);
+            bool mine = active && s >= 0;
+            const uint64_t am = gq_ballot(mine);
+            if (am) {
+                // the slot of the first updating lane, summed over every lane that updates it
+                const int lead = __builtin_ctzll(am);
+                const int sl = __builtin_amdgcn_readlane(s, lead);
+                const bool in = mine && s == sl;
+                const uint64_t same = gq_ballot(in);
+                if (__popcll(same) > 1) {
+                    const uint32_t cn = gq_wave_sum<uint32_t>(in ? 1u : 0u);
+                    const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
+                    const uint64_t lo = gq_wave_sum<uint64_t>(
+                        in ? static_cast<uint64_t>(static_cast<uint32_t>(static_cast<uint64_t>(rv[c]))) : 0ull);
+                    const int64_t hs = gq_wave_sum<int64_t>(in ? (rv[c] >> 32) : 0);
+                    if (gq_lane() == lead) lds_add_sums(T, sl, cn, sq, lo, hs);
+                    mine = mine && !in;
+                }
+            }
+            if (mine) lds_add_split(T, s, q[c], rv[c]);
             const bool spill = active && s < 0;
             const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
             if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
         }
+    }
+    if (split) {
+        __syncthreads();
+        for (int s = threadIdx.x; s < SLOTS; s += GB_BUCKET_THREADS) {
+            const bool occ = lds_occupied(T, s);
+            const int64_t k64 = occ ? lds_key64(T, s) : 0;
+            const int32_t k32 = occ ? lds_key32(T, s) : 0;
+            const int64_t gs = g_find<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32, status);
+            if (occ && gs >= 0) g_add(g, gs, T.cnt[s], T.sq[s], lds_split_total(T.lo[s], T.hi[s]));
+        }
+        return;
     }
     __syncthreads();
     // emit: each thread owns SLOTS / GB_BUCKET_THREADS consecutive slots
@@ -853,6 +967,8 @@ struct gb_plan {
     int64_t chunk_rows;     // rows per hist/scatter workgroup
     int words;              // 8-byte words per partitioned record
     uint64_t gslots;
+    int64_t bucket_chunk;   // rows per workgroup of a split bucket
+    int64_t bucket_grid;    // bucket-pass workgroups: P plus the most extra chunks n rows can need
 };
 
 gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
@@ -874,6 +990,12 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
         if (P > GB_CUS) P = (P + GB_CUS - 1) / GB_CUS * GB_CUS;
         pl.P = static_cast<int>(std::min<int64_t>(std::max<int64_t>(P, 2), GB_MAX_P_WIDE));
         pl.wide = pl.P > GB_MAX_P;
+        // a bucket with more than 4x the mean rows (and at least 64K) holds a
+        // heavy key: it is split into chunks of that many rows
+        const int64_t mean = (n + pl.P - 1) / pl.P;
+        pl.bucket_chunk = std::max<int64_t>(4 * mean, 65536);
+        pl.bucket_chunk = (pl.bucket_chunk + 4095) / 4096 * 4096;
+        pl.bucket_grid = pl.P + n / pl.bucket_chunk;
         if (pl.wide) {                      // 2048 chunks of whole tiles
             const int64_t tiles = pl.ntiles;
             const int64_t per = (tiles + 2047) / 2048;
@@ -889,6 +1011,7 @@ struct gb_ws {
     uint32_t *side_cnt;
     uint32_t *hist;
     uint32_t *start;
+    uint32_t *cstart;       // chunks of the bucket pass before each bucket
     void *scan_ws;
     uint64_t *recs;         // partitioned rows, narrow records
     uint32_t *side;         // row indices of wide rows
@@ -900,6 +1023,8 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     gb_ws w{};
     const size_t S = pl.gslots;
     w.g.state = c.take<uint32_t>(S);
+    w.side_cnt = c.take<uint32_t>(64);      // [0] wide rows; [16..23] scatter tile counters per XCD
+    w.zero_bytes = c.off;                   // the state words and counters start at zero
     w.g.k64 = c.take<int64_t>(k64 ? S : 1);
     w.g.k32 = c.take<int32_t>(k32 ? S : 1);
     w.g.cnt = c.take<uint64_t>(S);
@@ -907,12 +1032,11 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     w.g.lo = c.take<uint64_t>(S);
     w.g.hi = c.take<int64_t>(S);
     w.g.mask = S - 1;
-    w.side_cnt = c.take<uint32_t>(64);      // [0] wide rows; [16..23] scatter tile counters per XCD
-    w.zero_bytes = c.off;
     if (!pl.small) {
         const size_t rows = static_cast<size_t>(n > 0 ? n : 1);
         w.hist = c.take<uint32_t>(static_cast<size_t>(pl.ntiles) * static_cast<size_t>(pl.P));
         w.start = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
+        w.cstart = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
         w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, pl.P));
         w.recs = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
         w.side = c.take<uint32_t>(rows);
@@ -956,10 +1080,12 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(pl.P)),
+    GQ_TRY(gq_launch(ctx, "gq_groupby_chunks", gb_chunks_kernel, dim3(1), dim3(GB_BUCKET_THREADS), 0, s,
+                     static_cast<const uint32_t *>(w.start), pl.P, pl.bucket_chunk, w.cstart));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(pl.bucket_grid)),
                      dim3(GB_BUCKET_THREADS), 0, s, static_cast<const uint64_t *>(w.recs),
-                     static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.side_cnt), w.g, out,
-                     ctx->status_dev));
+                     static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.cstart), pl.P,
+                     pl.bucket_chunk, static_cast<const uint32_t *>(w.side_cnt), w.g, out, ctx->status_dev));
     return gq_launch(ctx, "gq_groupby_emit", gb_table_emit_kernel<K64, K32>, dim3(emit_blocks), dim3(256), 0, s, w.g,
                      out, ctx->status_dev);
 }

@@ -469,6 +469,45 @@ def test_groupby_large_path_wide_rows(ctx, composite, overflow):
     _check_groups(res, exp, composite, True)
 
 
+@pytest.mark.parametrize("composite,max_groups", [(False, 500_000), (True, 500_000), (False, 6_000_000),
+                                                  (True, 6_000_000)])
+def test_groupby_heavy_keys_split_buckets(ctx, composite, max_groups):
+    """Zipf-like heavy keys: one key holds 40% of the rows, others 10% and 5%.
+    Their buckets hold far more rows than the mean and are aggregated in
+    chunks by several workgroups whose partial groups merge in the global
+    table; lanes of a wave on the same key combine before their LDS update.
+    Some heavy-key rows are too wide for a narrow record.  Exact against the
+    oracle, with the tile-staged (500K groups) and the chunked (6M) scatter."""
+    r = rng(71 + int(composite) + (2 if max_groups > 1_000_000 else 0))
+    n = nv = 2_000_000
+    keys = np.unique(r.integers(0, 1 << 31, size=200_000)).astype(np.int32)
+    pick = r.random(n)
+    key32 = keys[r.integers(0, len(keys), size=n)]
+    key32[pick < 0.40] = keys[0]
+    key32[(pick >= 0.40) & (pick < 0.50)] = keys[1]
+    key32[(pick >= 0.50) & (pick < 0.55)] = keys[2]
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    heavy_rows = np.nonzero(pick < 0.40)[0][:300]
+    qty[rowid[heavy_rows[:150]]] = 1 << 40                     # wide rows of the heaviest key
+    price[rowid[heavy_rows[150:]]] = (1 << 62) - 5
+    if composite:
+        g32 = r.integers(0, 2, size=n).astype(np.int32)
+        key64 = key32.astype(np.int64) * 1_000_003 - 11
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key32=g32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                                key32=dev(g32), max_groups=max_groups)
+    else:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                                max_groups=max_groups)
+    assert ctx.status() == gq.GQ_OK
+    assert exp["count"].max() >= 0.2 * n
+    _check_groups(res, exp, composite, True)
+
+
 @pytest.mark.parametrize("qlo", [-(1 << 31), 0])
 @pytest.mark.parametrize("groups", [25, 5000, 150_000])
 def test_groupby_signed_revenues_in_narrow_records(ctx, groups, qlo):
