@@ -36,6 +36,7 @@ constexpr int GB_SMALL_SLOTS = 1024;
 constexpr int64_t GB_SMALL_GROUPS = 512;
 constexpr int GB_ITEMS = 16;
 constexpr int GB_TILE = GB_THREADS * GB_ITEMS;       // rows per small-path pass
+constexpr int GB_SMALL_BATCH = 8;                    // rows per thread whose loads overlap
 constexpr int GB_BUCKET_THREADS = 1024;
 constexpr int GB_LDS_PROBES = 64;
 
@@ -374,18 +375,46 @@ __global__ __launch_bounds__(GB_THREADS) void gb_small_kernel(gb_args a, gtable 
     const int64_t n = eff_n(a.n_bound, a.n_dev);
     const int64_t step = static_cast<int64_t>(gridDim.x) * GB_TILE;
     for (int64_t j0 = static_cast<int64_t>(blockIdx.x) * GB_TILE; j0 < n; j0 += step) {
-#pragma unroll 4
-        for (int c = 0; c < GB_ITEMS; ++c) {
-            const int64_t j = j0 + c * GB_THREADS + threadIdx.x;
-            bool active = j < n && row_pass(a, value_row(a, j));
-            gb_row<K64, K32> r{};
-            if (active) r = load_row<K64, K32>(a, j);
-            const uint64_t h = gb_hash(r.k64, r.k32);
-            const int s = lds_find(T, active, h, r.k64, r.k32);
-            if (active && s >= 0) lds_add(T, s, 1u, static_cast<uint64_t>(r.qty), r.rev);
-            const bool spill = active && s < 0;
-            const int64_t gs = g_find<K64, K32>(g, spill, h, r.k64, r.k32, status);
-            if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(r.qty), r.rev);
+        // groups of 8 rows per thread: row ids, then keys and values, all in
+        // flight together before the LDS work
+        for (int c0 = 0; c0 < GB_ITEMS; c0 += GB_SMALL_BATCH) {
+            int64_t v[GB_SMALL_BATCH];
+            bool act[GB_SMALL_BATCH];
+#pragma unroll
+            for (int c = 0; c < GB_SMALL_BATCH; ++c) {
+                const int64_t j = j0 + (c0 + c) * GB_THREADS + threadIdx.x;
+                act[c] = j < n;
+                v[c] = act[c] ? value_row(a, j) : 0;
+            }
+            if (a.filter) {
+#pragma unroll
+                for (int c = 0; c < GB_SMALL_BATCH; ++c) act[c] = act[c] && row_pass(a, v[c]);
+            }
+            int64_t k64[GB_SMALL_BATCH], qv[GB_SMALL_BATCH], pv[GB_SMALL_BATCH], dv[GB_SMALL_BATCH];
+            int32_t k32[GB_SMALL_BATCH];
+#pragma unroll
+            for (int c = 0; c < GB_SMALL_BATCH; ++c) {
+                const int64_t j = j0 + (c0 + c) * GB_THREADS + threadIdx.x;
+                k64[c] = qv[c] = pv[c] = dv[c] = 0;
+                k32[c] = 0;
+                if (act[c]) {
+                    k64[c] = K64 ? a.key64[a.key64_by_rowid ? v[c] : j] : 0;
+                    k32[c] = K32 ? a.key32[a.key32_by_rowid ? v[c] : j] : 0;
+                    qv[c] = a.qty[v[c]];
+                    pv[c] = a.price[v[c]];
+                    dv[c] = a.disc[v[c]];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < GB_SMALL_BATCH; ++c) {
+                const gq_i128 rev = gq_revenue(pv[c], a.rev_scale, dv[c]);
+                const uint64_t h = gb_hash(k64[c], k32[c]);
+                const int s = lds_find(T, act[c], h, k64[c], k32[c]);
+                if (act[c] && s >= 0) lds_add(T, s, 1u, static_cast<uint64_t>(qv[c]), rev);
+                const bool spill = act[c] && s < 0;
+                const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
+                if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(qv[c]), rev);
+            }
         }
     }
     __syncthreads();
@@ -748,22 +777,46 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_wide_kernel(gb_args a, 
     const int64_t c0 = static_cast<int64_t>(chunk) * chunk_rows;
     const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
     for (int64_t base = c0; base < c1; base += TILE) {
-#pragma unroll 4
+        // all loads of the thread's rows first (row ids, then keys and values),
+        // so that they are in flight together
+        int64_t vr[ITEMS];
+        bool keep[ITEMS];
+#pragma unroll
         for (int c = 0; c < ITEMS; ++c) {
             const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            if (j >= c1) continue;
-            const int64_t v = value_row(a, j);
-            if (!row_pass(a, v)) continue;
-            const int64_t k64 = K64 ? a.key64[a.key64_by_rowid ? v : j] : 0;
-            const int32_t k32 = K32 ? a.key32[a.key32_by_rowid ? v : j] : 0;
-            const int64_t qty = a.qty[v];
-            const gq_i128 rev = gq_revenue(a.price[v], a.rev_scale, a.disc[v]);
-            const bool nar = is_narrow(qty, rev);
+            keep[c] = j < c1;
+            vr[c] = keep[c] ? value_row(a, j) : 0;
+        }
+        if (a.filter) {
+#pragma unroll
+            for (int c = 0; c < ITEMS; ++c) keep[c] = keep[c] && row_pass(a, vr[c]);
+        }
+        int64_t k64[ITEMS], qv[ITEMS], pv[ITEMS], dv[ITEMS];
+        int32_t k32[ITEMS];
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            const int64_t j = base + c * GB_THREADS + threadIdx.x;
+            k64[c] = qv[c] = pv[c] = dv[c] = 0;
+            k32[c] = 0;
+            if (keep[c]) {
+                k64[c] = K64 ? a.key64[a.key64_by_rowid ? vr[c] : j] : 0;
+                k32[c] = K32 ? a.key32[a.key32_by_rowid ? vr[c] : j] : 0;
+                qv[c] = a.qty[vr[c]];
+                pv[c] = a.price[vr[c]];
+                dv[c] = a.disc[vr[c]];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            if (!keep[c]) continue;
+            const int64_t j = base + c * GB_THREADS + threadIdx.x;
+            const gq_i128 rev = gq_revenue(pv[c], a.rev_scale, dv[c]);
+            const bool nar = is_narrow(qv[c], rev);
             if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
             uint64_t w[W];
-            make_words<K64, K32>(w, k64, k32, nar ? static_cast<int32_t>(qty) : 0,
+            make_words<K64, K32>(w, k64[c], k32[c], nar ? static_cast<int32_t>(qv[c]) : 0,
                                  nar ? static_cast<int64_t>(rev.lo) : 0);
-            const uint32_t pos = atomicAdd(&cursor[gb_bucket(gb_hash(k64, k32), P)], 1u);
+            const uint32_t pos = atomicAdd(&cursor[gb_bucket(gb_hash(k64[c], k32[c]), P)], 1u);
 #pragma unroll
             for (int x = 0; x < W; ++x) recs[static_cast<int64_t>(pos) * W + x] = w[x];
         }
