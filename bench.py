@@ -136,6 +136,10 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--probe", default="auto", choices=["auto", "ordered", "partitioned"],
                     help="join probe form (auto = ordered, the faster one on MI355X)")
+    ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
+                    help="plain form: 2 overlaps the join build and the top-k with the fact-side chain "
+                         "(with 1, the two-stream step is also timed and reported beside it)")
+    ap.add_argument("--load-factor", type=float, default=0.5, help="join hash table load factor bound")
     ap.add_argument("--no-partition", action="store_true",
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -175,7 +179,8 @@ def main():
     print(f"# generated {w.fact.n:,} x {w.dim_m:,} rows in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
           flush=True)
     pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, log2_fanout=w.log2_fanout, topk=100,
-                       partition=not args.no_partition, probe=args.probe)
+                       partition=not args.no_partition, probe=args.probe, streams=args.streams,
+                       load_factor=args.load_factor)
 
     for _ in range(args.warmup):
         pl.step()
@@ -206,6 +211,24 @@ def main():
 
     by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100, partition=not args.no_partition)
     total_bytes = sum(by.values())
+    two_stream = None
+    if args.streams == 1:
+        # the same chain with the build and the top-k on a second stream
+        for _ in range(args.warmup):
+            pl.step(streams=2)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(args.steps):
+            pl.step(streams=2)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        ctx.raise_status()
+        ms2 = f0.elapsed_time(f1) / args.steps
+        two_stream = {"ms_per_step": round(ms2, 4), "GB/s": round(total_bytes / (ms2 * 1e6), 1),
+                      "frac_of_peak": round(total_bytes / (ms2 * 1e6) / HBM_PEAK_GBS, 4),
+                      "overlap": "join build beside partition+filter; top-k beside probe+group-by"}
+        print(f"# two streams: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
     kern = {}
     if not args.no_timing:
         for k in KERNELS:
@@ -244,8 +267,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "fact_rows": w.fact.n, "dim_rows": w.dim_m, "groups": groups,
                    "selected_rows": s_n, "buckets": 1 << w.log2_fanout, "filter": f"date < {w.date_hi}",
-                   "topk": 100, "form": "plain (one launch chain per operator)",
-                   "partitioned": not args.no_partition, "probe": pl.probe,
+                   "topk": 100, "form": f"plain (one launch chain per operator, {args.streams} streams)",
+                   "partitioned": not args.no_partition, "probe": pl.probe, "load_factor": args.load_factor,
                    "partition_items": int(os.environ.get("GQ_PARTITION_ITEMS", "16"))},
         "hbm_frac_of_peak": round(total_bytes / (ms_step * 1e6) / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_step": total_bytes,
@@ -253,6 +276,7 @@ def main():
         "ops": ops,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
         "roofline": roofline,
+        "two_streams": two_stream,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -285,7 +309,8 @@ def bench_skew(args):
     max_groups = 16_000_000
     groups = gq.alloc_groups(ctx, max_groups, True, True)
     ws_gb = ctx.workspace(gq.lib().gq_groupby_workspace_bytes(n, max_groups, 1, 1))
-    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, partition=False, topk=100)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=w.attr_range, partition=False, topk=100,
+                       streams=args.streams)
 
     def composite():
         gq.gq_groupby_agg(ctx, fact["qty"], fact["price"], fact["disc"], key64=fact["fk"], key32=fact["g32"],
@@ -342,7 +367,7 @@ def bench_skew(args):
         "data": "synthetic",
         "config": {"workload": w.name, "fact_rows": n, "dim_rows": w.dim_m, "composite_groups": ng,
                    "selected_rows": s_n, "filter": f"date < {w.date_hi}", "topk": 100,
-                   "form": "plain (one launch chain per operator)", "probe": pl.probe},
+                   "form": f"plain (one launch chain per operator, {args.streams} streams)", "probe": pl.probe},
         "hbm_frac_of_peak": round(total / (ms_step * 1e6) / HBM_PEAK_GBS, 4),
         "algorithmic_bytes_per_step": total,
         "composite_groupby": {"ms": round(ms_gb, 4), "bytes": by_gb, "GB/s": round(by_gb / (ms_gb * 1e6), 1),

@@ -12,6 +12,13 @@ single-pass one.
 
 All buffers and workspaces are allocated once, so a step allocates nothing and
 never waits for the host: every count travels on the device.
+
+With streams=2 the operators that do not depend on each other overlap: the
+join build (it reads only the dimension table) runs on a second stream beside
+the partition and filter, and the top-k (it needs only the filter's selection)
+runs there beside the probe and group-by.  Events order them; each operator is
+still its own launch chain, and the step ends when both streams are done
+(joined into the caller's current stream).
 """
 from __future__ import annotations
 
@@ -26,11 +33,15 @@ FACT_COLS = ("date", "qty", "price", "disc")
 class PlainPipeline:
     def __init__(self, ctx: Context, fact: dict, dim: dict, date_hi: int, max_groups: int,
                  log2_fanout: int = 6, topk: int = 100, load_factor: float = 0.5, partition: bool = True,
-                 probe: str = "auto"):
+                 probe: str = "auto", streams: int = 1):
         self.ctx, self.fact, self.dim = ctx, fact, dim
         self.date_hi, self.max_groups, self.log2p = date_hi, max_groups, log2_fanout
         self.k, self.partition = topk, partition
+        if streams not in (1, 2):
+            raise ValueError(f"streams must be 1 or 2, not {streams}")
+        self.streams = streams
         d = ctx.device
+        self.side = None
         n, m = fact["fk"].numel(), dim["key"].numel()
         self.n, self.m = n, m
         L = lib()
@@ -71,14 +82,41 @@ class PlainPipeline:
         f = self.fact
         return f["fk"], f["date"], f["qty"], f["price"], f["disc"]
 
-    def step(self):
+    def _build(self):
+        gq_join_build(self.ctx, self.dim["key"], self.dim["attr"], table=self.table, ws=self.ws_build)
+
+    def _topk(self, price):
+        gq_topk(self.ctx, price, self.k, sel=self.sel, n=self.n, n_dev=self.n_sel, val_out=self.tk_val,
+                rowid_out=self.tk_row, n_out=self.tk_n, ws=self.ws_tk)
+
+    def step(self, streams: int | None = None):
+        """One pass of the chain; `streams` overrides the pipeline's setting."""
         ctx, f = self.ctx, self.fact
+        two = (streams or self.streams) == 2
+        main = torch.cuda.current_stream(ctx.device)
+        if two and self.side is None:
+            self.side = torch.cuda.Stream(device=ctx.device)          # default priority
+            self.ev_fork, self.ev_built, self.ev_sel, self.ev_done = (torch.cuda.Event() for _ in range(4))
+        if two:                                          # build beside partition + filter
+            self.ev_fork.record(main)
+            self.side.wait_event(self.ev_fork)
+            with torch.cuda.stream(self.side):
+                self._build()
+                self.ev_built.record(self.side)
         if self.partition:
             gq_radix_partition(ctx, f["fk"], self.log2p, [f[c] for c in FACT_COLS],
                                outs=(self.p_key, self.p_cols, self.p_rowid, self.p_off), ws=self.ws_part)
         fk, date, qty, price, disc = self.columns()
         gq_filter(ctx, date, -(1 << 31), self.date_hi, out=self.sel, n_out=self.n_sel, ws=self.ws_filter)
-        gq_join_build(ctx, self.dim["key"], self.dim["attr"], table=self.table, ws=self.ws_build)
+        if two:                                          # top-k beside probe + group-by
+            self.ev_sel.record(main)
+            if self.k:
+                self.side.wait_event(self.ev_sel)
+                with torch.cuda.stream(self.side):
+                    self._topk(price)
+            main.wait_event(self.ev_built)
+        else:
+            self._build()
         if self.probe == "partitioned":
             gq_join_probe_partitioned(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel,
                                       log2_fanout=self.log2p if self.partition else 0, prow=self.prow,
@@ -88,9 +126,11 @@ class PlainPipeline:
                           payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
         gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,
                        max_groups=self.max_groups, out=self.groups, ws=self.ws_gb)
-        if self.k:
-            gq_topk(ctx, price, self.k, sel=self.sel, n=self.n, n_dev=self.n_sel, val_out=self.tk_val,
-                    rowid_out=self.tk_row, n_out=self.tk_n, ws=self.ws_tk)
+        if two:
+            self.ev_done.record(self.side)
+            main.wait_event(self.ev_done)
+        elif self.k:
+            self._topk(price)
 
     def source_rows(self, rows: torch.Tensor) -> torch.Tensor:
         """Map row ids of the (possibly partitioned) columns to input row ids."""

@@ -54,11 +54,12 @@ def _tables(w, device):
     return fact, dim
 
 
-@pytest.mark.parametrize("probe", ["ordered", "partitioned"])
-def test_small_workload_every_stage(ctx, probe):
+@pytest.mark.parametrize("probe,streams", [("ordered", 2), ("partitioned", 2), ("partitioned", 1)])
+def test_small_workload_every_stage(ctx, probe, streams):
     w = synth.workload(0)
     fact, dim = _tables(w, "cuda")
-    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, log2_fanout=w.log2_fanout, topk=100, probe=probe)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, log2_fanout=w.log2_fanout, topk=100, probe=probe,
+                       streams=streams)
     pl.step()
     assert ctx.status() == gq.GQ_OK
     hf = {k: H(v) for k, v in fact.items()}
@@ -102,9 +103,14 @@ def test_small_workload_partitioning_does_not_change_the_join(ctx):
 
 
 def test_pipeline_repeated_steps_identical(ctx):
+    """Steps queued back to back with no host wait between them (the build and
+    the top-k of one step on the second stream must not overlap the next
+    step's partition and filter), then every step's outputs compared."""
     w = synth.workload(0, scale=0.25)
     fact, dim = _tables(w, "cuda")
-    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, topk=100)
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, topk=100, streams=2)
+    for _ in range(4):
+        pl.step()
     outs = []
     for _ in range(3):
         pl.step()
