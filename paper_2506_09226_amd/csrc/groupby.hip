@@ -907,16 +907,30 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
     lds_init(T);
     __syncthreads();
     constexpr int STEP = GB_BUCKET_THREADS * GB_BUCKET_ITEMS;
+    // the records of the next step are loaded while this step's are aggregated
+    int64_t nk64[GB_BUCKET_ITEMS], nq[GB_BUCKET_ITEMS], nrv[GB_BUCKET_ITEMS];
+    int32_t nk32[GB_BUCKET_ITEMS];
+    auto load_step = [&](int64_t i0) {
+#pragma unroll
+        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+            const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
+            nk64[c] = nq[c] = nrv[c] = 0;
+            nk32[c] = 0;
+            if (i < r1) read_words<K64, K32>(recs, i, nk64[c], nk32[c], nq[c], nrv[c]);
+        }
+    };
+    load_step(r0);
     for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
         int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
         int32_t k32[GB_BUCKET_ITEMS];
 #pragma unroll
         for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
-            const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
-            k64[c] = q[c] = rv[c] = 0;
-            k32[c] = 0;
-            if (i < r1) read_words<K64, K32>(recs, i, k64[c], k32[c], q[c], rv[c]);
+            k64[c] = nk64[c];
+            k32[c] = nk32[c];
+            q[c] = nq[c];
+            rv[c] = nrv[c];
         }
+        load_step(i0 + STEP);
 #pragma unroll
         for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
             const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;

@@ -836,8 +836,11 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
                                                                 int32_t *__restrict__ prow_out,
                                                                 int32_t *__restrict__ pay_out, int64_t *n_out)
 {
-    __shared__ int32_t pay[JX_TILE];                      // payloads in probe order; then the staged payloads
-    __shared__ uint16_t stage_i[JX_TILE];                 // in-tile index of each staged match
+    // LDS index x is stored at x + x / 16: a thread's 16 consecutive elements
+    // then start 17 words after its neighbour's, on another bank
+    __shared__ int32_t pay[JX_TILE + JX_TILE / 16];       // payloads in probe order; then the staged payloads
+    __shared__ uint16_t stage_i[JX_TILE + JX_TILE / 16];  // in-tile index of each staged match
+    auto pad = [](uint32_t x) { return x + (x >> 4); };
     __shared__ uint32_t hitw[JX_TILE / 32];               // hit bitmap in probe order
     __shared__ uint32_t scan_smem[JX_THREADS / 64];
     __shared__ uint32_t s_next;
@@ -883,7 +886,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
         for (int c = 0; c < JX_ITEMS; ++c) {
             const int64_t p = base + c * JX_THREADS + threadIdx.x;
             if (p < n) {
-                pay[ix[c]] = static_cast<int32_t>(rv[c]);
+                pay[pad(ix[c])] = static_cast<int32_t>(rv[c]);
                 if (rv[c] >= 0) atomicOr(&hitw[ix[c] >> 5], 1u << (ix[c] & 31));
             }
         }
@@ -899,7 +902,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
         const uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & 0xffffu;
         int32_t my_pay[JX_ITEMS];
 #pragma unroll
-        for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[elem0 + i];
+        for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[pad(elem0 + i)];
         uint32_t total;
         uint32_t pos = gq_block_exclusive_scan_lds<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
         if (wave == 0) {
@@ -910,8 +913,8 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
 #pragma unroll
         for (int i = 0; i < JX_ITEMS; ++i) {
             if (mine & (1u << i)) {
-                stage_i[pos] = static_cast<uint16_t>(elem0 + i);
-                pay[pos] = my_pay[i];
+                stage_i[pad(pos)] = static_cast<uint16_t>(elem0 + i);
+                pay[pad(pos)] = my_pay[i];
                 ++pos;
             }
         }
@@ -926,9 +929,9 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
                 rw[c] = 0;
                 py[c] = 0;
                 if (i < tot) {
-                    const int64_t e = base + stage_i[i];
+                    const int64_t e = base + stage_i[pad(i)];
                     rw[c] = HAS_SEL ? sel[e] : static_cast<int32_t>(e);
-                    py[c] = pay[i];
+                    py[c] = pay[pad(i)];
                 }
             }
 #pragma unroll
