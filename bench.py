@@ -138,7 +138,7 @@ def main():
                     help="join probe form (auto = ordered, the faster one on MI355X)")
     ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
                     help="plain form: 2 overlaps the join build and the top-k with the fact-side chain "
-                         "(with 1, the two-stream step is also timed and reported beside it)")
+                         "(per-kernel times then include the overlap)")
     ap.add_argument("--load-factor", type=float, default=0.5, help="join hash table load factor bound")
     ap.add_argument("--no-partition", action="store_true",
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
@@ -211,24 +211,6 @@ def main():
 
     by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100, partition=not args.no_partition)
     total_bytes = sum(by.values())
-    two_stream = None
-    if args.streams == 1:
-        # the same chain with the build and the top-k on a second stream
-        for _ in range(args.warmup):
-            pl.step(streams=2)
-        torch.cuda.synchronize()
-        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        f0.record(stream)
-        for _ in range(args.steps):
-            pl.step(streams=2)
-        f1.record(stream)
-        torch.cuda.synchronize()
-        ctx.raise_status()
-        ms2 = f0.elapsed_time(f1) / args.steps
-        two_stream = {"ms_per_step": round(ms2, 4), "GB/s": round(total_bytes / (ms2 * 1e6), 1),
-                      "frac_of_peak": round(total_bytes / (ms2 * 1e6) / HBM_PEAK_GBS, 4),
-                      "overlap": "join build beside partition+filter; top-k beside probe+group-by"}
-        print(f"# two streams: {ms2:.3f} ms/step", file=sys.stderr, flush=True)
     kern = {}
     if not args.no_timing:
         for k in KERNELS:
@@ -276,7 +258,6 @@ def main():
         "ops": ops,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
         "roofline": roofline,
-        "two_streams": two_stream,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
