@@ -1,11 +1,13 @@
 // Scan + filter: ordered stream compaction of a range predicate.
 //
-// One pass over the column.  A tile of FT_TILE rows is read with coalesced
-// loads (wave w, step c reads rows c*256 + w*64 + lane), each wave's ballot
-// becomes one 64-bit word of a tile bitmap in LDS, each thread then owns 32
-// consecutive rows of the bitmap, a block scan gives in-tile output slots,
-// a decoupled look-back over tiles gives the tile's global offset, and the
-// compacted row ids are staged in LDS and written out contiguously.
+// One pass over the column.  A workgroup takes FT_GROUP consecutive tiles of
+// FT_TILE rows with one dequeue.  Each tile is read with coalesced loads (wave
+// w, step c reads rows c*256 + w*64 + lane) and each wave's ballot becomes one
+// 64-bit word of the tile's bitmap in LDS.  The group's match count goes
+// through a decoupled look-back over groups, which gives its global offset;
+// then, tile by tile, each thread owns 32 consecutive rows of the bitmap, a
+// block scan gives output slots, and the compacted row ids are staged in LDS
+// and written out contiguously.
 #include "gq_device.h"
 #include "gq_internal.h"
 
@@ -15,6 +17,7 @@ constexpr int FT_THREADS = 256;
 constexpr int FT_ITEMS = 32;
 constexpr int FT_TILE = FT_THREADS * FT_ITEMS;     // 8192 rows
 constexpr int FT_WORDS = FT_TILE / 64;              // 128 bitmap words
+constexpr int FT_GROUP = 4;                         // tiles per dequeue
 
 struct filter_ws {
     uint32_t *tile_ctr;
@@ -37,10 +40,10 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
                                                             int64_t hi, int32_t *__restrict__ out,
                                                             int64_t *n_out, uint32_t *tile_ctr, uint64_t *status)
 {
-    __shared__ uint64_t bits[FT_WORDS];
+    __shared__ uint64_t bits[FT_GROUP][FT_WORDS];
     __shared__ int32_t stage[FT_TILE];
     __shared__ uint32_t scan_smem[FT_THREADS / 64];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_group;
     __shared__ uint64_t s_goff;
 
     int64_t n = n_bound;
@@ -48,52 +51,73 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
         const int64_t d = *n_dev;
         n = d < n_bound ? (d > 0 ? d : 0) : n_bound;
     }
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    __syncthreads();
-    const uint32_t t = s_tile;
     const int64_t ntiles = (n + FT_TILE - 1) / FT_TILE;
-    if (static_cast<int64_t>(t) >= ntiles) {
-        if (t == 0 && threadIdx.x == 0) *n_out = 0;
+    const int64_t ngroups = (ntiles + FT_GROUP - 1) / FT_GROUP;
+    if (ntiles == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = 0;
         return;
     }
-    const int64_t base = static_cast<int64_t>(t) * FT_TILE;
+    // One dequeue per group of FT_GROUP consecutive tiles (atomics on one
+    // address serialize chip-wide).  The group is one unit of the look-back:
+    // its bitmaps are built first, its match count is published, and only
+    // then does it wait for its predecessors (groups are numbered in dequeue
+    // order, so each predecessor is done or held by a running workgroup).
+    if (threadIdx.x == 0) s_group = atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const int64_t g = s_group;
+    if (g >= ngroups) return;                              // same value in every thread
+    const int64_t t0 = g * FT_GROUP;
+    const int nt = static_cast<int>(ntiles - t0 < FT_GROUP ? ntiles - t0 : FT_GROUP);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-
-    T v[FT_ITEMS];
+    uint32_t cnt = 0;                                      // this thread's matches over the group
+    for (int i = 0; i < nt; ++i) {
+        const int64_t base = (t0 + i) * FT_TILE;
+        T v[FT_ITEMS];
 #pragma unroll
-    for (int c = 0; c < FT_ITEMS; ++c) {
-        const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
-        v[c] = 0;
-        if (e < n) v[c] = col[HAS_SEL ? static_cast<int64_t>(sel_in[e]) : e];
-    }
+        for (int c = 0; c < FT_ITEMS; ++c) {
+            const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
+            v[c] = 0;
+            if (e < n) v[c] = col[HAS_SEL ? static_cast<int64_t>(sel_in[e]) : e];
+        }
 #pragma unroll
-    for (int c = 0; c < FT_ITEMS; ++c) {
-        const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
-        const int64_t x = static_cast<int64_t>(v[c]);
-        const uint64_t b = gq_ballot(e < n && lo <= x && x < hi);
-        if (lane == 0) bits[c * (FT_THREADS / 64) + wave] = b;
+        for (int c = 0; c < FT_ITEMS; ++c) {
+            const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
+            const int64_t x = static_cast<int64_t>(v[c]);
+            const uint64_t b = gq_ballot(e < n && lo <= x && x < hi);
+            if (lane == 0) bits[i][c * (FT_THREADS / 64) + wave] = b;
+        }
     }
     __syncthreads();
-
-    // thread i owns tile rows [32 i, 32 i + 32)
-    uint32_t mine = static_cast<uint32_t>(bits[threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32));
-    uint32_t total;
-    uint32_t pos = gq_block_exclusive_scan<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+    // thread i owns rows [32 i, 32 i + 32) of every tile
+    for (int i = 0; i < nt; ++i)
+        cnt += __popc(static_cast<uint32_t>(bits[i][threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32)));
+    uint32_t gtotal;
+    (void)gq_block_exclusive_scan<FT_THREADS>(cnt, &gtotal, scan_smem);
     if (wave == 0) {
-        const uint64_t g = gq_lookback(status, t, total);
-        if (lane == 0) s_goff = g;
-    }
-    const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * 32;
-    while (mine) {
-        const int i = __builtin_ctz(mine);
-        mine &= mine - 1;
-        const int64_t e = row0 + i;
-        stage[pos++] = HAS_SEL ? sel_in[e] : static_cast<int32_t>(e);
+        const uint64_t go = gq_lookback(status, static_cast<uint32_t>(g), gtotal);
+        if (lane == 0) s_goff = go;
     }
     __syncthreads();
-    const int64_t goff = static_cast<int64_t>(s_goff);
-    for (uint32_t i = threadIdx.x; i < total; i += FT_THREADS) out[goff + i] = stage[i];
-    if (static_cast<int64_t>(t) == ntiles - 1 && threadIdx.x == 0) *n_out = goff + total;
+    int64_t goff = static_cast<int64_t>(s_goff);
+    for (int i = 0; i < nt; ++i) {
+        const int64_t base = (t0 + i) * FT_TILE;
+        uint32_t mine = static_cast<uint32_t>(bits[i][threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32));
+        uint32_t total;
+        uint32_t pos =
+            gq_block_exclusive_scan<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+        const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * 32;
+        while (mine) {
+            const int k = __builtin_ctz(mine);
+            mine &= mine - 1;
+            const int64_t e = row0 + k;
+            stage[pos++] = HAS_SEL ? sel_in[e] : static_cast<int32_t>(e);
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < total; k += FT_THREADS) out[goff + k] = stage[k];
+        goff += total;
+        __syncthreads();                                   // stage[] is free for the next tile
+    }
+    if (g == ngroups - 1 && threadIdx.x == 0) *n_out = goff;
 }
 
 template <typename T, bool S>
@@ -101,7 +125,8 @@ gq_status launch_filter(gq_ctx *ctx, const void *col, const int32_t *sel_in, int
                         int64_t lo, int64_t hi, int32_t *out, int64_t *n_out, filter_ws w, hipStream_t s)
 {
     const int64_t tiles = (n + FT_TILE - 1) / FT_TILE;
-    const uint32_t grid = static_cast<uint32_t>(tiles > 0 ? tiles : 1);
+    const int64_t groups = (tiles + FT_GROUP - 1) / FT_GROUP;
+    const uint32_t grid = static_cast<uint32_t>(groups > 0 ? groups : 1);
     return gq_launch(ctx, "gq_filter", filter_kernel<T, S>, dim3(grid), dim3(FT_THREADS), 0, s,
                      static_cast<const T *>(col), sel_in, n, n_dev, lo, hi, out, n_out, w.tile_ctr, w.status);
 }

@@ -584,7 +584,8 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
 // records in LDS in bucket order, then write them out as contiguous runs
 // starting at the tile's offset gofs[t * P + b] in each bucket.
 // Persistent: XCD x (workgroups b with b mod 8 = x) takes one contiguous
-// eighth of the tiles, in order, from its own counter (xctr[x]), so a
+// eighth of the tiles, in order, from its own counter (xctr[32 x], one
+// 128-byte line per counter), so a
 // bucket's runs from neighbouring tiles reach one L2 close together in time
 // and leave it as whole lines.  The row ids, directly indexed keys and bucket
 // offsets of a workgroup's next tile are loaded while it scatters the current
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
             pgo[i] = (t < r1 && b < P) ? gofs[t * P + b] : 0u;
         }
     };
-    if (threadIdx.x == 0) s_next = atomicAdd(&xctr[xcd], 1u);
+    if (threadIdx.x == 0) s_next = atomicAdd(&xctr[32 * xcd], 1u);
     __syncthreads();
     int64_t t = r0 + static_cast<int64_t>(gq_uniform(s_next));
     int32_t v[ITEMS];
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
         gq_lds_barrier();                               // opens each pass (thread-0 work never merges across passes)
         const int64_t base = t * TILE;
         uint32_t nxt = 0;
-        if (threadIdx.x == 0) nxt = atomicAdd(&xctr[xcd], 1u);   // the next tile, dequeued early
+        if (threadIdx.x == 0) nxt = atomicAdd(&xctr[32 * xcd], 1u);   // the next tile, dequeued early
         // every thread has read s_next (the current tile) and finished the
         // last tile's LDS reads
         gq_lds_barrier();
@@ -1090,7 +1091,9 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     gb_ws w{};
     const size_t S = pl.gslots;
     w.g.state = c.take<uint32_t>(S);
-    w.side_cnt = c.take<uint32_t>(64);      // [0] wide rows; [16..23] scatter tile counters per XCD
+    // [0] wide rows; [32 (x + 1)] the scatter's tile counter of XCD x, one
+    // 128-byte line each
+    w.side_cnt = c.take<uint32_t>(32 * (GQ_NUM_XCD + 1));
     w.zero_bytes = c.off;                   // the state words and counters start at zero
     w.g.k64 = c.take<int64_t>(k64 ? S : 1);
     w.g.k32 = c.take<int32_t>(k32 ? S : 1);
@@ -1143,7 +1146,7 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
         GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>,
                          dim3(static_cast<uint32_t>(std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3)))), dim3(GB_THREADS), 0, s,
                          a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt,
-                         w.side_cnt + 16));
+                         w.side_cnt + 32));
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));
