@@ -40,7 +40,8 @@ def rng(seed):
 
 # ------------------------------------------------------------------ filter ---
 
-@pytest.mark.parametrize("n", [0, 1, 63, 8191, 8192, 8193, 100_003, 1_000_000])
+@pytest.mark.parametrize("n", [0, 1, 63, 8191, 8192, 8193, 32767, 32768, 32769, 40963, 100_003, 1_000_000,
+                               3_000_001])
 @pytest.mark.parametrize("dtype", [np.int32, np.int64])
 def test_filter(ctx, n, dtype):
     r = rng(n)
@@ -62,6 +63,21 @@ def test_filter_with_selection_and_device_count(ctx, n):
     exp = oracle.filter(col, -10, 400, sel_in=sel_in[:used])
     n_dev = torch.tensor([used], dtype=torch.int64, device="cuda")
     out, cnt = gq.gq_filter(ctx, dev(col), -10, 400, sel_in=dev(sel_in), n_dev=n_dev)
+    k = int(cnt.item())
+    assert k == len(exp) and np.array_equal(host(out, k), exp)
+
+
+@pytest.mark.parametrize("used", [0, 1, 8192, 40_000, 65_537])
+def test_filter_device_count_far_below_bound(ctx, used):
+    """The grid is sized by the bound (300,000 rows, ten groups of four tiles);
+    the device count ends inside an early group, at a group edge, or at zero,
+    and the groups past it do nothing."""
+    n = 300_000
+    col = rng(used + 3).integers(0, 2557, size=n).astype(np.int32)
+    exp = oracle.filter(col[:used], 0, 1500)
+    n_dev = torch.tensor([used], dtype=torch.int64, device="cuda")
+    out, cnt = gq.gq_filter(ctx, dev(col), 0, 1500, n_dev=n_dev)
+    assert ctx.status() == gq.GQ_OK
     k = int(cnt.item())
     assert k == len(exp) and np.array_equal(host(out, k), exp)
 
