@@ -8,7 +8,10 @@ The probe is the single-pass one (gq_join_probe) or the partitioned one
 (gq_join_probe_partitioned: table regions probed from LDS); both give the
 same output.  "auto" takes the partitioned probe when the fact table was
 radix-partitioned (then the probe stream is in region order), otherwise the
-single-pass one.
+single-pass one.  "tune" times both on the first step's data (HIP events, one
+host wait) and keeps the faster: a heavy key concentrates its table region's
+probes on one workgroup of the partitioned form, while the single-pass form
+reads a hot slot from cache.
 
 All buffers and workspaces are allocated once, so a step allocates nothing and
 never waits for the host: every count travels on the device.
@@ -61,11 +64,14 @@ class PlainPipeline:
         self.n_join = torch.zeros(1, dtype=torch.int64, device=d)
         if probe == "auto":
             probe = "partitioned" if partition else "ordered"
-        if probe not in ("ordered", "partitioned"):
-            raise ValueError(f"probe must be auto, ordered or partitioned, not {probe!r}")
+        if probe not in ("ordered", "partitioned", "tune"):
+            raise ValueError(f"probe must be auto, tune, ordered or partitioned, not {probe!r}")
         self.probe = probe
-        self.ws_probe = ctx.workspace(L.gq_join_probe_partitioned_workspace_bytes(n) if probe == "partitioned"
-                                      else L.gq_join_probe_workspace_bytes(n))
+        self.probe_ms = None                     # with "tune": each form's time on the first step
+        self.ws_probe = {}
+        for form in (("ordered", "partitioned") if probe == "tune" else (probe,)):
+            self.ws_probe[form] = ctx.workspace(L.gq_join_probe_partitioned_workspace_bytes(n)
+                                                if form == "partitioned" else L.gq_join_probe_workspace_bytes(n))
         self.groups = alloc_groups(ctx, max_groups, False, True)
         self.ws_gb = ctx.workspace(L.gq_groupby_workspace_bytes(n, max_groups, 0, 1))
         if topk:
@@ -88,6 +94,31 @@ class PlainPipeline:
     def _topk(self, price):
         gq_topk(self.ctx, price, self.k, sel=self.sel, n=self.n, n_dev=self.n_sel, val_out=self.tk_val,
                 rowid_out=self.tk_row, n_out=self.tk_n, ws=self.ws_tk)
+
+    def _probe(self, form, fk):
+        ctx = self.ctx
+        if form == "partitioned":
+            gq_join_probe_partitioned(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel,
+                                      log2_fanout=self.log2p if self.partition else 0, prow=self.prow,
+                                      payload=self.pay, n_out=self.n_join, ws=self.ws_probe[form])
+        else:
+            gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
+                          payload=self.pay, n_out=self.n_join, ws=self.ws_probe[form])
+
+    def _tune_probe(self, fk, stream):
+        """Run both probe forms (same output), time each, keep the faster."""
+        ms = {}
+        for form in ("ordered", "partitioned"):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            self._probe(form, fk)
+            e1.record(stream)
+            e1.synchronize()
+            ms[form] = e0.elapsed_time(e1)
+        self.probe_ms = ms
+        self.probe = min(ms, key=ms.get)
+        if self.probe == "ordered":              # the partitioned form ran last: redo the winner's output
+            self._probe("ordered", fk)
 
     def step(self, streams: int | None = None):
         """One pass of the chain; `streams` overrides the pipeline's setting."""
@@ -117,13 +148,10 @@ class PlainPipeline:
             main.wait_event(self.ev_built)
         else:
             self._build()
-        if self.probe == "partitioned":
-            gq_join_probe_partitioned(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel,
-                                      log2_fanout=self.log2p if self.partition else 0, prow=self.prow,
-                                      payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
+        if self.probe == "tune":
+            self._tune_probe(fk, main)
         else:
-            gq_join_probe(ctx, self.table, fk, sel=self.sel, n=self.n, n_dev=self.n_sel, prow=self.prow,
-                          payload=self.pay, n_out=self.n_join, ws=self.ws_probe)
+            self._probe(self.probe, fk)
         gq_groupby_agg(ctx, qty, price, disc, n=self.n, n_dev=self.n_join, rowid=self.prow, key32=self.pay,
                        max_groups=self.max_groups, out=self.groups, ws=self.ws_gb)
         if two:

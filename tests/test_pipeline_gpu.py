@@ -54,7 +54,7 @@ def _tables(w, device):
     return fact, dim
 
 
-@pytest.mark.parametrize("probe,streams", [("ordered", 2), ("partitioned", 2), ("partitioned", 1)])
+@pytest.mark.parametrize("probe,streams", [("ordered", 2), ("partitioned", 2), ("partitioned", 1), ("tune", 1)])
 def test_small_workload_every_stage(ctx, probe, streams):
     w = synth.workload(0)
     fact, dim = _tables(w, "cuda")
@@ -87,6 +87,10 @@ def test_small_workload_every_stage(ctx, probe, streams):
     # top-k
     ev, er = oracle.topk(pprice, 100, sel=esel)
     assert np.array_equal(H(pl.tk_val), ev) and np.array_equal(H(pl.tk_row), er)
+    if probe == "tune":                          # the tuner timed both forms and kept one
+        assert set(pl.probe_ms) == {"ordered", "partitioned"} and pl.probe in pl.probe_ms
+        pl.step()
+        assert np.array_equal(H(pl.prow, nj), eprow) and np.array_equal(H(pl.pay, nj), epay)
 
 
 def test_small_workload_partitioning_does_not_change_the_join(ctx):
