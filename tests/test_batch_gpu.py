@@ -154,3 +154,51 @@ def test_batch_duplicate_key_reported(ctx):
     b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
     b.run()
     assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
+
+
+def test_batch_full_size_sampled(ctx, tmp_path):
+    """The benchmark's batched workload at full size (512 instances, build
+    sizes log-uniform in [1e3, 2e6], probe sizes 8-16x build: 1.75G probe
+    rows) in the benchmark's launch configuration (autotuned).  Every
+    instance: its group counts and sums equal totals over its selected rows
+    computed separately (every foreign key names a key of its own instance, so
+    |join| = |selection|).  The smallest, the largest and one instance drawn
+    at random: element by element against the oracle."""
+    spec = synth.BatchSpec()
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    assert len(layout) == 512
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.autotune(str(tmp_path / "batch_tuning.txt"))
+    b.run()
+    torch.cuda.synchronize()
+    assert ctx.status() == gq.GQ_OK
+    res = b.results()
+    keep = cols["date"] < spec.date_hi
+    zero = torch.zeros((), dtype=torch.int64, device="cuda")
+    cs_cnt = torch.cumsum(keep.to(torch.int64), 0)
+    cs_qty = torch.cumsum(torch.where(keep, cols["qty"], zero), 0)
+    cs_rev = torch.cumsum(torch.where(keep, cols["price"] * (100 - cols["disc"]), zero), 0)
+    del keep
+    ends = torch.tensor([no + n - 1 for _, _, no, n in layout], dtype=torch.int64, device="cuda")
+    starts = torch.tensor([no - 1 for _, _, no, _ in layout], dtype=torch.int64, device="cuda")
+
+    def seg(cs):
+        hi = cs[ends].cpu().numpy()
+        lo = np.where(starts.cpu().numpy() >= 0, cs[starts.clamp(min=0)].cpu().numpy(), 0)
+        return hi - lo
+
+    e_cnt, e_qty, e_rev = seg(cs_cnt), seg(cs_qty), seg(cs_rev)
+    for i, g in enumerate(res):
+        assert int(g["count"].sum()) == e_cnt[i], i
+        assert int(g["sum_qty"].sum()) == e_qty[i], i
+        assert bool((g["sum_rev_hi"] == 0).all()) and int(g["sum_rev_lo"].astype(np.int64).sum()) == e_rev[i], i
+    del cs_cnt, cs_qty, cs_rev
+    sizes = [m for _, m, _, _ in layout]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.random.default_rng(5).integers(0, len(layout)))}
+    for i in sorted(pick):
+        mo, m, no, n = layout[i]
+        h = {k: cols[k][a:a + c].cpu().numpy() for k, a, c in
+             (("dim_key", mo, m), ("dim_attr", mo, m), ("fk", no, n), ("date", no, n), ("qty", no, n),
+              ("price", no, n), ("disc", no, n))}
+        e = _oracle(h, (0, m, 0, n), spec)
+        _equal(_sorted(res[i]), e)
