@@ -131,3 +131,99 @@ def test_served_rejects_bad_queries(served):
     with pytest.raises(gq.GQError):
         srv.submit(QuerySpec(gq.GQ_QUERY_FILTER_AGG, 100, max_groups=5000))
     srv.close()
+
+
+def test_served_full_size_each_template():
+    """The served workload at full size: 1.6B resident fact rows with two
+    200M-row dimensions and both join tables resident, one query per template
+    submitted together through the served path (continuous batching, two
+    streams).  Expected groups are exact int64 totals over every selected row,
+    each fact row mapped to its dimension rows by recomputing the generator's
+    counter-based draw (no operator of this library takes part); sampled groups
+    and the top-100 are also recomputed by the oracle on the rows they cover."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gq.Context(0)
+    spec = synth.ServeSpec()
+    fact, dim1, dim2 = synth.serve_tables(spec, device="cuda")
+    t1 = gq.gq_join_build(ctx, dim1["key"], dim1["attr"])
+    t2 = gq.gq_join_build(ctx, dim2["key"], dim2["attr"])
+    torch.cuda.synchronize()
+    assert ctx.status() == gq.GQ_OK
+    del dim1, dim2
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    pool = torch.empty(int(min(free - (8 << 30), 100 << 30)) & ~255, dtype=torch.uint8, device="cuda")
+    date_hi = 700                                            # 27.4% of the rows
+    qs = [QuerySpec(gq.GQ_QUERY_FILTER_AGG, date_hi, max_groups=16),
+          QuerySpec(gq.GQ_QUERY_JOIN_AGG, date_hi, max_groups=spec.code_range),
+          QuerySpec(gq.GQ_QUERY_JOIN2_AGG, date_hi, max_groups=32),
+          QuerySpec(gq.GQ_QUERY_FILTER_TOPK, date_hi, k=100)]
+    srv = Server(0, fact, t1, t2, pool, streams=2, max_batch=16)
+    subs = [srv.submit(q) for q in qs]
+    for s_ in subs:
+        srv.wait(s_)
+        assert s_.status == gq.GQ_OK
+    got = [result_host(s_) for s_ in subs]
+    srv.close()
+    del pool
+    torch.cuda.empty_cache()
+
+    n, m = spec.n, spec.m
+    z = {"disc": 11, "code": spec.code_range, "attr2": spec.attr_range}
+    exp = {g: [torch.zeros(c, dtype=torch.int64, device="cuda") for _ in range(3)] for g, c in z.items()}
+    sample_codes = torch.tensor([0, 777_777, spec.code_range - 1], dtype=torch.int64, device="cuda")
+    sample_rows = []
+    top_keys = []
+    chunk = 1 << 27
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        rows = torch.arange(a, b, dtype=torch.int64, device="cuda")
+        keep = fact["date"][a:b] < date_hi
+        r = rows[keep]
+        qty, price, disc = fact["qty"][a:b][keep], fact["price"][a:b][keep], fact["disc"][a:b][keep]
+        rev = price * (100 - disc)
+        code = synth.uniform_int(spec.seed, synth.S_DIM_ATTR, synth.uniform_int(spec.seed, synth.S_FK_ROW, r, 0, m - 1),
+                                 0, spec.code_range - 1)
+        attr2 = synth.uniform_int(spec.seed + 1, synth.S_DIM_ATTR,
+                                  synth.uniform_int(spec.seed, synth.S_FK2_ROW, r, 0, m - 1), 0, spec.attr_range - 1)
+        for g, key in (("disc", disc), ("code", code), ("attr2", attr2)):
+            for acc, v in zip(exp[g], (torch.ones_like(qty), qty, rev)):
+                acc.scatter_add_(0, key, v)
+        sample_rows.append(r[torch.isin(code, sample_codes)])
+        k = price * (1 << 31) + ((1 << 31) - 1 - r)            # unique: price desc, then row asc
+        top_keys.append(torch.topk(k, min(100, k.numel())).values)
+        del rows, keep, r, qty, price, disc, rev, code, attr2, k
+
+    def check(res, g, keyname):
+        cnt, sq, rv = (x.cpu().numpy() for x in exp[g])
+        present = np.nonzero(cnt)[0]
+        order = np.argsort(res[keyname], kind="stable")
+        assert np.array_equal(res[keyname][order], present)
+        assert np.array_equal(res["count"][order], cnt[present])
+        assert np.array_equal(res["sum_qty"][order], sq[present])
+        assert np.array_equal(res["sum_rev_lo"][order].astype(np.int64), rv[present])
+        assert bool((res["sum_rev_hi"] == 0).all())
+        return order
+
+    check(got[0], "disc", "key64")
+    order = check(got[1], "code", "key32")
+    check(got[2], "attr2", "key32")
+    # sampled join+agg groups, recomputed by the oracle on their rows
+    rows = torch.cat(sample_rows).cpu().numpy()
+    hf = {c: fact[c][torch.from_numpy(rows).cuda()].cpu().numpy() for c in ("qty", "price", "disc")}
+    codes = synth.uniform_int(spec.seed, synth.S_DIM_ATTR,
+                              synth.uniform_int(spec.seed, synth.S_FK_ROW, torch.from_numpy(rows), 0, m - 1),
+                              0, spec.code_range - 1).to(torch.int32).numpy()
+    e = oracle.groupby(len(rows), hf["qty"], hf["price"], hf["disc"], key32=codes)
+    g1 = {f: v[order] for f, v in got[1].items() if v is not None}
+    at = np.searchsorted(g1["key32"], e["key32"])
+    for f in ("key32", "count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
+        assert np.array_equal(g1[f][at], e[f]), f
+    np.testing.assert_allclose(g1["avg_rev"][at], e["avg_rev"], rtol=AVG_RTOL, atol=0)
+    # top-100: the oracle over the candidate rows (the best 100 keys of every chunk)
+    best = torch.topk(torch.cat(top_keys), 100).values
+    cand = np.sort(((1 << 31) - 1 - (best % (1 << 31))).cpu().numpy())
+    ev, er = oracle.topk(fact["price"][torch.from_numpy(cand).cuda()].cpu().numpy(), 100)
+    assert np.array_equal(got[3]["row"], cand[er]) and np.array_equal(got[3]["val"], ev)
+    ctx.close()
