@@ -51,7 +51,8 @@ OP_KERNELS = {
     "join_build": ["gq_join_build_init", "gq_join_build_insert", "gq_join_build_part_hist",
                    "gq_join_build_part_scan", "gq_join_build_part_offsets", "gq_join_build_part_scatter",
                    "gq_join_build_bounds", "gq_join_build_regions", "gq_join_build_overflow"],
-    "join_probe": ["gq_join_probe", "gq_join_probe_split", "gq_join_probe_regions", "gq_join_probe_compact"],
+    "join_probe": ["gq_join_probe", "gq_join_probe_split", "gq_join_probe_plan", "gq_join_probe_regions",
+                   "gq_join_probe_compact"],
     "groupby": ["gq_groupby_hist", "gq_groupby_scan", "gq_groupby_scatter", "gq_groupby_side", "gq_groupby_chunks",
                 "gq_groupby_bucket",
                 "gq_groupby_emit", "gq_groupby_local"],

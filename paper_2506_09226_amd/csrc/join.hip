@@ -494,6 +494,9 @@ constexpr int JX_MAX_H = 8;                             // high-part bits (bound
 constexpr int JX_LISTS = (1 << JX_MAX_S) + 1;           // sub-region lists + the stray list
 constexpr int JX_STARTS = 260;                          // per tile: list starts (JX_LISTS + 1 used)
 constexpr int JX_WIN = 2048;                            // region kernel: entries per window
+constexpr uint32_t JX_HEAVY_RUN = 256;                  // a tile's run longer than this counts to its region's weight
+constexpr int JX_MAX_REGIONS = 1 << (JX_MAX_H + JX_MAX_S);
+constexpr int JX_PLAN_THREADS = 1024;
 
 struct jx_geom {
     int L;                  // log2 table slots
@@ -503,10 +506,12 @@ struct jx_geom {
 };
 
 struct jx_ws {
-    uint32_t *ctr;          // [0] region counter, [32] compaction tile counter
+    uint32_t *ctr;          // [0] region counter, [16] heavy-run flag, [32] compaction tile counter
     uint32_t *hp_first;     // per high part: ntiles - first tile (0: none)
     uint32_t *hp_end;       // per high part: last tile + 1 (0: none)
     uint64_t *status;       // compaction look-back words, one per tile
+    uint32_t *rw;           // per region: probe rows in its heavy runs (runs > JX_HEAVY_RUN rows)
+    uint32_t *iprefix;      // per region: work items before it; [nregions] = all items
     int32_t *tile_hp;       // high part of each tile's lists, -1 for an empty tile
     uint16_t *starts;       // per tile: JX_STARTS list starts
     int64_t *skey;          // pool: probe keys
@@ -524,6 +529,8 @@ jx_ws jx_layout(gq_carver &c, int64_t n)
     w.hp_first = c.take<uint32_t>(1 << JX_MAX_H);
     w.hp_end = c.take<uint32_t>(1 << JX_MAX_H);
     w.status = c.take<uint64_t>(static_cast<size_t>(w.ntiles));
+    w.rw = c.take<uint32_t>(JX_MAX_REGIONS);
+    w.iprefix = c.take<uint32_t>(JX_MAX_REGIONS + 1);
     w.tile_hp = c.take<int32_t>(static_cast<size_t>(w.ntiles));     // first word after the zeroed prefix
     w.starts = c.take<uint16_t>(static_cast<size_t>(w.ntiles) * JX_STARTS);
     w.skey = c.take<int64_t>(static_cast<size_t>(rows));
@@ -643,6 +650,14 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
         }
         tot[j] = run;
     }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {                         // a heavy key's region: its long runs are weighed
+        const int x = 2 * threadIdx.x + j;
+        if (x < (1 << gm.S) && tot[j] > JX_HEAVY_RUN) {
+            atomicAdd(&w.rw[(hp << gm.S) + x], tot[j]);
+            __hip_atomic_store(&w.ctr[16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
     uint32_t all;
     const uint32_t excl = gq_block_exclusive_scan<JX_THREADS>(tot[0] + tot[1], &all, scan_smem);
     lstart[2 * threadIdx.x] = excl;
@@ -677,7 +692,35 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
     }
 }
 
-// Region probes from LDS (see above).  Persistent: regions come from w.ctr[0].
+// Work items of the region pass: a region whose heavy runs hold more than
+// item_rows probe rows (a heavy key's region) becomes ceil(weight / item_rows)
+// items over equal ranges of its high part's tiles; every other region is one
+// item.  iprefix[r] = items before region r.  One workgroup.
+__global__ __launch_bounds__(JX_PLAN_THREADS) void jx_plan_kernel(const uint32_t *__restrict__ rw, int nregions,
+                                                                  uint32_t item_rows, const uint32_t *heavy,
+                                                                  uint32_t *__restrict__ iprefix)
+{
+    __shared__ uint32_t scan_smem[JX_PLAN_THREADS / 64];
+    if (*heavy == 0u) {                                    // no heavy run anywhere: one item per region
+        if (threadIdx.x == 0) iprefix[nregions] = static_cast<uint32_t>(nregions);
+        return;
+    }
+    const int per = (nregions + JX_PLAN_THREADS - 1) / JX_PLAN_THREADS;   // consecutive regions per thread
+    const int r0 = static_cast<int>(threadIdx.x) * per;
+    auto items = [&](int r) { return rw[r] > item_rows ? (rw[r] + item_rows - 1) / item_rows : 1u; };
+    uint32_t mine = 0;
+    for (int r = r0; r < r0 + per && r < nregions; ++r) mine += items(r);
+    uint32_t total;
+    uint32_t run = gq_block_exclusive_scan<JX_PLAN_THREADS>(mine, &total, scan_smem);
+    for (int r = r0; r < r0 + per && r < nregions; ++r) {
+        iprefix[r] = run;
+        run += items(r);
+    }
+    if (threadIdx.x == 0) iprefix[nregions] = total;
+}
+
+// Region probes from LDS (see above).  Persistent: work items (a region, or
+// one tile range of a heavy region) come from w.ctr[0].
 __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table, jx_geom gm, jx_ws w)
 {
     __shared__ __align__(16) int64_t lkey[JX_REGION];
@@ -690,14 +733,27 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
     if (static_cast<const jt_header *>(table)->log2_slots != static_cast<uint32_t>(gm.L)) return;   // uniform
     const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
     const uint64_t mask = (1ull << gm.L) - 1;
+    const uint32_t nitems = static_cast<uint32_t>(gq_uniform(w.iprefix[gm.nregions]));   // written by the plan pass
     // As in every persistent loop here, a barrier opens each pass so the
     // thread-0 dequeue never merges with thread-0 work of the previous pass.
     while (true) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = static_cast<int64_t>(atomicAdd(&w.ctr[0], 1u));
         __syncthreads();
-        const int64_t item = gq_uniform(s_item);
-        if (item >= gm.nregions) break;
+        const uint32_t wi = static_cast<uint32_t>(gq_uniform(s_item));
+        if (wi >= nitems) break;                           // same value in every thread
+        int64_t item = wi;                                 // the region (with no split region, the item itself)
+        uint32_t part = 0, nparts = 1;                     // this item's share of the region's tiles
+        if (nitems != static_cast<uint32_t>(gm.nregions)) {
+            item = 0;                                      // last r with iprefix[r] <= wi
+            for (int64_t hi = gm.nregions - 1; item < hi;) {
+                const int64_t mid = (item + hi + 1) >> 1;
+                if (w.iprefix[mid] <= wi) item = mid;
+                else hi = mid - 1;
+            }
+            part = wi - w.iprefix[item];
+            nparts = w.iprefix[item + 1] - w.iprefix[item];
+        }
         const uint32_t hp = static_cast<uint32_t>(item) >> gm.S;
         const uint32_t sub = static_cast<uint32_t>(item) & ((1u << gm.S) - 1);
         const jt_slot *rs = slots + (static_cast<uint64_t>(item) << JX_RBITS);
@@ -707,8 +763,11 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
             lpay[j] = v.z;
         }
         const uint32_t first_c = w.hp_first[hp], end = w.hp_end[hp];
-        const int64_t t_lo = gq_uniform(first_c ? w.ntiles - static_cast<int64_t>(first_c) : 0);
-        const int64_t t_hi = gq_uniform(static_cast<int64_t>(end));
+        const int64_t hp_lo = gq_uniform(first_c ? w.ntiles - static_cast<int64_t>(first_c) : 0);
+        const int64_t hp_hi = gq_uniform(static_cast<int64_t>(end));
+        const int64_t span = hp_hi > hp_lo ? (hp_hi - hp_lo + nparts - 1) / nparts : 0;
+        const int64_t t_lo = hp_lo + static_cast<int64_t>(part) * span;
+        const int64_t t_hi = t_lo + span < hp_hi ? t_lo + span : hp_hi;
         // the run of list `sub` in tile t (length 0 if t is not a tile of this high part)
         auto run_of = [&](int64_t t, uint32_t &len, int32_t &at) {
             len = 0;
@@ -1083,8 +1142,15 @@ gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table
     else
         GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s,
                          table, fk, n, n_dev, sel, gm, w, ctx->status_dev));
+    // a region with more rows in heavy runs than 4x the mean region (and at
+    // least 65,536) is split into items of that many rows
+    const int64_t item_rows = std::max<int64_t>(65536, 4 * (n / gm.nregions));
+    GQ_TRY(gq_launch(ctx, "gq_join_probe_plan", jx_plan_kernel, dim3(1), dim3(JX_PLAN_THREADS), 0, s,
+                     static_cast<const uint32_t *>(w.rw), gm.nregions,
+                     static_cast<uint32_t>(std::min<int64_t>(item_rows, 1ll << 31)),
+                     static_cast<const uint32_t *>(w.ctr + 16), w.iprefix));
     const int64_t want = static_cast<int64_t>(ctx->num_cus) * 3;      // three 52-KB-LDS workgroups per CU
-    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(want, gm.nregions));
+    const uint32_t grid = static_cast<uint32_t>(want);
     GQ_TRY(gq_launch(ctx, "gq_join_probe_regions", jx_region_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, gm,
                      w));
     // persistent compaction: four workgroups per CU (122 VGPRs)

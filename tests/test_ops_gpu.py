@@ -236,17 +236,27 @@ def test_join_empty_sides(ctx):
     (2_000_000, 1_000_000, "random", 6, 0.5),    # wrong order for the hint: nearly all rows stray
     (2_000_000, 1_000_000, "random", 2, 0.5),    # 4 high parts: three quarters stray
     (1_800_000, 2_500_000, "partitioned", 6, 0.9),   # long probe runs: many cross a region's end
+    (2_000_000, 3_000_000, "heavy", 6, 0.5),         # heavy keys: their regions are split into several items
+    (1_800_000, 2_500_000, "heavy", 6, 0.9),
+    (400_000, 1_000_000, "heavy", 0, 0.5),
 ])
 def test_join_probe_partitioned(ctx, m, n, order, fanout, lf):
     """The partitioned probe returns exactly the output of the ordered probe
     (the oracle, in probe order): with and without a selection, with misses,
     with a device count, on a probe stream in radix-partition order and on a
-    random one, with regions held in LDS and with the fallbacks."""
+    random one, with regions held in LDS and with the fallbacks, and with
+    heavy keys (40%, 10% and 5% of the probes) whose regions the region pass
+    splits across workgroups."""
     r = rng(m + 7 * n + fanout)
     bkey, bpay = _dim(m, m + 3)
     fk = np.where(r.random(n) < 0.85, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
     fk = fk.astype(np.int64)
-    if order == "partitioned":                 # stable order by the top `fanout` hash bits, as after the partition
+    if order == "heavy":
+        u = r.random(n)
+        fk[u < 0.40] = bkey[7]
+        fk[(u >= 0.40) & (u < 0.50)] = bkey[m // 2]
+        fk[(u >= 0.50) & (u < 0.55)] = bkey[m - 1]
+    if order in ("partitioned", "heavy"):      # stable order by the top `fanout` hash bits, as after the partition
         fk = fk[np.argsort(_fmix64_np(fk) >> np.uint64(64 - fanout), kind="stable")]
     table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), load_factor=lf)
     sel = np.sort(r.choice(n, size=(2 * n) // 3, replace=False)).astype(np.int32)
