@@ -24,5 +24,13 @@ gq_status gq_partition_bits(gq_ctx *ctx, const int64_t *key, int64_t n, int log2
 // offsets of each (tile, bucket) run; start[0..P] receives the bucket starts
 // (start[P] = total).  P <= 8192.  ws: gq_tile_offsets_workspace(ntiles, P).
 size_t gq_tile_offsets_workspace(int64_t ntiles, int P);
+// Optional: only the first ceil(min(*n_dev, n_bound) / tile_rows) of the
+// ntiles tiles hold counts (the rows arrive as a device count); the rest are
+// neither read nor written.
+struct gq_tile_count {
+    const int64_t *n_dev;
+    int64_t n_bound;
+    int64_t tile_rows;
+};
 gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
-                          hipStream_t s, const char *name);
+                          hipStream_t s, const char *name, const gq_tile_count *live = nullptr);

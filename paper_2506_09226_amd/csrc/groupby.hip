@@ -562,6 +562,7 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
     __syncthreads();
     const int64_t n = eff_n(a.n_bound, a.n_dev);
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk_rows;
+    if (c0 >= n) return;                                   // past the row count: no counts (the scan skips it)
     const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
     for (int64_t base = c0; base < c1; base += TILE) {
 #pragma unroll 4
@@ -1137,7 +1138,8 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
     else
         GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P>, dim3(grid), dim3(GB_THREADS), 0,
                          s, a, pl.P, pl.chunk_rows, w.hist));
-    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, pl.P, w.start, w.scan_ws, s, "gq_groupby_scan"));
+    const gq_tile_count live{a.n_dev, a.n_bound, pl.chunk_rows};     // tiles past the device row count are idle
+    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, pl.P, w.start, w.scan_ws, s, "gq_groupby_scan", &live));
     if (pl.wide)
         GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_wide_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0,
                          s, a, pl.P, pl.chunk_rows, static_cast<const uint32_t *>(w.hist), w.recs, w.side,

@@ -89,9 +89,20 @@ constexpr int TO_START_THREADS = 1024;
 // thread keeps that many independent loads in flight.
 constexpr int TO_BATCH = 32;
 
-__global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
-                                                                  int P, uint32_t *__restrict__ csum)
+// Tiles that hold counts: all ntiles, or those the device row count reaches.
+GQ_DEV int64_t to_live_tiles(int64_t ntiles, gq_tile_count live)
 {
+    if (!live.n_dev) return ntiles;
+    int64_t n = *live.n_dev;
+    n = n < 0 ? 0 : (n < live.n_bound ? n : live.n_bound);
+    const int64_t t = (n + live.tile_rows - 1) / live.tile_rows;
+    return t < ntiles ? t : ntiles;
+}
+
+__global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
+                                                                  int P, uint32_t *__restrict__ csum, gq_tile_count live)
+{
+    ntiles = to_live_tiles(ntiles, live);
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * TO_THREADS + threadIdx.x;
     if (b >= P) return;
@@ -150,8 +161,9 @@ __global__ __launch_bounds__(TO_START_THREADS) void to_bucket_start_kernel(const
 
 __global__ __launch_bounds__(TO_THREADS) void to_final_kernel(uint32_t *__restrict__ cnt, int64_t ntiles, int P,
                                                               const uint32_t *__restrict__ csum,
-                                                              const uint32_t *__restrict__ start)
+                                                              const uint32_t *__restrict__ start, gq_tile_count live)
 {
+    ntiles = to_live_tiles(ntiles, live);
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * TO_THREADS + threadIdx.x;
     if (b >= P) return;
@@ -182,8 +194,10 @@ size_t gq_tile_offsets_workspace(int64_t ntiles, int P)
 }
 
 gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
-                          hipStream_t s, const char *name)
+                          hipStream_t s, const char *name, const gq_tile_count *live)
 {
+    const gq_tile_count lv = live ? *live : gq_tile_count{nullptr, 0, 1};
+    if (live && live->tile_rows < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_tile_offsets: bad tile rows");
     if (P < 1 || P > TO_MAX_P || ntiles < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_tile_offsets: bad shape");
     gq_carver c(ws);
     const int64_t nchunks = (ntiles + TO_CHUNK - 1) / TO_CHUNK;
@@ -192,10 +206,10 @@ gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uin
     const dim3 grid2(static_cast<uint32_t>(nchunks), static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
     const dim3 grid1(static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
     GQ_TRY(gq_launch(ctx, name, to_chunk_sum_kernel, grid2, dim3(TO_THREADS), 0, s,
-                     static_cast<const uint32_t *>(cnt), ntiles, P, csum));
+                     static_cast<const uint32_t *>(cnt), ntiles, P, csum, lv));
     GQ_TRY(gq_launch(ctx, name, to_chunk_scan_kernel, grid1, dim3(TO_THREADS), 0, s, csum, nchunks, P, total));
     GQ_TRY(gq_launch(ctx, name, to_bucket_start_kernel, dim3(1), dim3(TO_START_THREADS), 0, s,
                      static_cast<const uint32_t *>(total), P, start));
     return gq_launch(ctx, name, to_final_kernel, grid2, dim3(TO_THREADS), 0, s, cnt, ntiles, P,
-                     static_cast<const uint32_t *>(csum), static_cast<const uint32_t *>(start));
+                     static_cast<const uint32_t *>(csum), static_cast<const uint32_t *>(start), lv);
 }
