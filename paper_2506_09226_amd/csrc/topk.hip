@@ -128,6 +128,13 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
         L.th_rk = 0;
     }
     gq_lds_barrier();
+    // the chunk of each workgroup, from the device row count when there is one
+    // (the host's chunk covers the bound and would leave workgroups idle)
+    if (n_dev) {
+        const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+        chunk = (per + TK_STEP - 1) / TK_STEP * TK_STEP;
+        if (chunk < TK_STEP) chunk = TK_STEP;
+    }
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
