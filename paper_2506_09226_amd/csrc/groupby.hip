@@ -618,9 +618,9 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
             pk64[c] = 0;
             pk32[c] = 0;
             if (t < r1 && j < n) {
-                pv[c] = a.rowid ? a.rowid[j] : static_cast<int32_t>(j);
-                if (K64 && !a.key64_by_rowid) pk64[c] = a.key64[j];
-                if (K32 && !a.key32_by_rowid) pk32[c] = a.key32[j];
+                pv[c] = a.rowid ? __builtin_nontemporal_load(&a.rowid[j]) : static_cast<int32_t>(j);
+                if (K64 && !a.key64_by_rowid) pk64[c] = __builtin_nontemporal_load(&a.key64[j]);
+                if (K32 && !a.key32_by_rowid) pk32[c] = __builtin_nontemporal_load(&a.key32[j]);
             }
         }
 #pragma unroll
@@ -657,9 +657,9 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
             if (keep[c]) {
                 if (K64 && a.key64_by_rowid) k64[c] = a.key64[v[c]];
                 if (K32 && a.key32_by_rowid) k32[c] = a.key32[v[c]];
-                qv[c] = a.qty[v[c]];
-                pv[c] = a.price[v[c]];
-                dv[c] = a.disc[v[c]];
+                qv[c] = __builtin_nontemporal_load(&a.qty[v[c]]);
+                pv[c] = __builtin_nontemporal_load(&a.price[v[c]]);
+                dv[c] = __builtin_nontemporal_load(&a.disc[v[c]]);
             }
         }
         int32_t nv[ITEMS];
