@@ -138,7 +138,9 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * chunk;
     int64_t j1 = j0 + chunk;
     if (j1 > n) j1 = n;
-    auto row_at = [&](int64_t j) -> int32_t { return j < j1 ? (sel ? sel[j] : static_cast<int32_t>(j)) : 0; };
+    auto row_at = [&](int64_t j) -> int32_t {
+        return j < j1 ? (sel ? __builtin_nontemporal_load(&sel[j]) : static_cast<int32_t>(j)) : 0;
+    };
     // pipeline: r0/v0 = step s (offered now), r1/v1 = step s+1, r2 = step s+2
     int32_t r0[TK_STEP_ITEMS], r1[TK_STEP_ITEMS], r2[TK_STEP_ITEMS];
     int64_t v0[TK_STEP_ITEMS], v1[TK_STEP_ITEMS];
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
 #pragma unroll
     for (int c = 0; c < TK_STEP_ITEMS; ++c) {
         const int64_t j = j0 + c * TK_THREADS + threadIdx.x;
-        v0[c] = j < j1 ? val[r0[c]] : 0;
+        v0[c] = j < j1 ? __builtin_nontemporal_load(&val[r0[c]]) : 0;
     }
     for (int64_t s = j0; s < j1; s += TK_STEP) {
 #pragma unroll
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
 #pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
             const int64_t j = s + TK_STEP + c * TK_THREADS + threadIdx.x;
-            v1[c] = j < j1 ? val[r1[c]] : 0;
+            v1[c] = j < j1 ? __builtin_nontemporal_load(&val[r1[c]]) : 0;
         }
         const uint64_t th_ok = L.th_ok;
         const uint32_t th_rk = L.th_rk;
