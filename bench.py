@@ -142,6 +142,8 @@ def main():
                     help="plain form: 2 overlaps the join build and the top-k with the fact-side chain "
                          "(per-kernel times then include the overlap)")
     ap.add_argument("--load-factor", type=float, default=0.5, help="join hash table load factor bound")
+    ap.add_argument("--graph", action="store_true",
+                    help="plain form: time replays of the step captured as one HIP graph (no per-kernel times)")
     ap.add_argument("--no-partition", action="store_true",
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -195,6 +197,13 @@ def main():
 
     # timed region: whole steps, stream-ordered, no host waits inside
     stream = torch.cuda.current_stream()
+    run_step = pl.step
+    if args.graph:
+        pl.capture()
+        for _ in range(args.warmup):
+            pl.replay()
+        run_step = pl.replay
+        args.no_timing = True                    # kernel events are not recorded inside a graph
     if not args.no_timing:
         ctx.reset_timing()
         ctx.set_timing(True)
@@ -203,7 +212,7 @@ def main():
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        pl.step()
+        run_step()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -253,7 +262,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "fact_rows": w.fact.n, "dim_rows": w.dim_m, "groups": groups,
                    "selected_rows": s_n, "buckets": 1 << w.log2_fanout, "filter": f"date < {w.date_hi}",
-                   "topk": 100, "form": f"plain (one launch chain per operator, {args.streams} streams)",
+                   "topk": 100, "form": f"plain (one launch chain per operator, {args.streams} streams"
+                                         f"{', captured as one HIP graph' if args.graph else ''})",
                    "partitioned": not args.no_partition, "probe": pl.probe, "probe_tuning_ms": pl.probe_ms,
                    "load_factor": args.load_factor,
                    "partition_items": int(os.environ.get("GQ_PARTITION_ITEMS", "16"))},

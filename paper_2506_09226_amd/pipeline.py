@@ -160,6 +160,24 @@ class PlainPipeline:
         elif self.k:
             self._topk(price)
 
+    def capture(self, streams: int | None = None):
+        """Capture one step into a HIP graph; replay() then runs the whole chain
+        with one launch.  Every operator's work is kernels on the capturing
+        stream (and the second stream, joined back by events), counts stay on
+        the device and nothing is allocated, so a replay recomputes the step
+        on whatever the input buffers hold.  The probe tuner decides first."""
+        if self.probe == "tune":
+            self.step(streams)
+        torch.cuda.synchronize(self.ctx.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step(streams)
+        torch.cuda.synchronize(self.ctx.device)
+        self.graph = g
+
+    def replay(self):
+        self.graph.replay()
+
     def source_rows(self, rows: torch.Tensor) -> torch.Tensor:
         """Map row ids of the (possibly partitioned) columns to input row ids."""
         return self.p_rowid[rows.long()] if self.partition else rows

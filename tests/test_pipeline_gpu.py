@@ -279,3 +279,33 @@ def test_one_gpu_share_full_size_sampled(ctx, probe):
     assert int((psel > t).sum().item()) < 100 <= cand.numel()
     ev, er = oracle.topk(H(pprice), 100, sel=H(cand))
     assert np.array_equal(v, ev) and np.array_equal(r, er)
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_pipeline_graph_replays_equal_eager(ctx, streams):
+    """The step captured as one HIP graph: three replays, with eager steps of
+    another pipeline and host synchronizations between them, each equal to
+    the eager step's outputs (partition, join, groups, top-k)."""
+    w = synth.workload(0, scale=0.5)
+    fact, dim = _tables(w, "cuda")
+    pl = PlainPipeline(ctx, fact, dim, w.date_hi, max_groups=64, topk=100, streams=streams, probe="tune")
+    pl.step()
+    pl.step()
+    torch.cuda.synchronize()
+    ref = (_sorted_groups(pl.groups.host()), H(pl.tk_row).copy(), H(pl.p_key).copy(),
+           H(pl.prow, int(pl.n_join.item())).copy())
+    other = PlainPipeline(ctx, fact, dim, 700, max_groups=64, topk=10)
+    pl.capture()
+    for _ in range(3):
+        for t in (pl.prow, pl.pay, pl.tk_row, pl.p_key):
+            t.zero_()
+        pl.replay()
+        torch.cuda.synchronize()
+        assert ctx.status() == gq.GQ_OK
+        got = (_sorted_groups(pl.groups.host()), H(pl.tk_row).copy(), H(pl.p_key).copy(),
+               H(pl.prow, int(pl.n_join.item())).copy())
+        _assert_groups_equal(got[0], ref[0], ("key32",))
+        for a, b in zip(got[1:], ref[1:]):
+            assert np.array_equal(a, b)
+        other.step()
+        torch.cuda.synchronize()
