@@ -1051,8 +1051,10 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
     pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
     pl.words = k64 ? 3 : 2;
     if (!pl.small) {
-        // about 60% of a bucket's LDS table for the expected groups
-        const int64_t per_bucket = (k64 ? 3072 : 4096) * 6 / 10;
+        // about 40% of a bucket's LDS table for the expected groups: the
+        // bucket pass waits on the longest probe chain of 64 lanes, so short
+        // chains pay for the extra buckets
+        const int64_t per_bucket = (k64 ? 3072 : 4096) * 4 / 10;
         int64_t P = (max_groups + per_bucket - 1) / per_bucket;
         // one 1024-thread workgroup per bucket and one per CU at a time: a
         // whole number of rounds over the CUs leaves no idle tail
