@@ -1,6 +1,7 @@
 """Benchmark of the relational hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload 1] [--no-cpu-baseline]
+                    [--no-batched] [--no-served] [--mode plain|batch|serve|skew]
 
 A step is one pass of the plain per-operator pipeline over the one-GPU share
 (200M fact rows x 25M dim rows, ~1.5M groups, 64 buckets), inputs resident in
@@ -13,6 +14,18 @@ HBM before timing starts:
 Prints one JSON line.  `value` is the whole step's algorithmic HBM bytes (what
 each operator must read and write once) divided by the step time.  Per-kernel
 durations come from HIP events recorded on the stream each kernel runs on.
+
+The same line carries the other two forms of the metric, measured in the same
+run after the plain steps (each on its own resident tables, the previous
+form's memory released first):
+  "batched"  512 join+aggregate instances in one persistent launch (autotuned)
+             against one launch chain per instance, results compared;
+  "served"   the served mix over a 1.6-billion-row resident fact table under
+             Poisson arrivals at 0.8 and 1.5 times the serial capacity, p50/p99
+             latency and throughput against serial plain execution, results
+             compared;
+plus the GPU clocks read before and after the GPU work, and the CPU baseline:
+the oracle timed on the host's cores, one core and all cores.
 """
 from __future__ import annotations
 
@@ -90,31 +103,125 @@ def load_traffic(kernel: str, workload: str):
         return None
 
 
-def cpu_baseline(w, sample_rows: int) -> dict:
-    """The oracle, single threaded, on the first `sample_rows` fact rows with the
-    full dimension table; reported in the same unit (algorithmic GB/s)."""
-    import numpy as np
+def gpu_clocks() -> dict:
+    """Current GPU clocks, power and temperature as rocm-smi reports them
+    (read only; an empty dict if the tool is unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showtemp", "--json"],
+                           capture_output=True, text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except Exception as e:                                    # noqa: BLE001 - a missing tool is not an error
+        return {"error": str(e)[:120]}
+    out = {}
+    for card, kv in data.items():
+        if not isinstance(kv, dict):
+            continue
+        keep = {}
+        for k, v in kv.items():
+            kl = k.lower()
+            if any(t in kl for t in ("sclk", "mclk", "fclk", "socclk", "power", "temperature (sensor junction)",
+                                     "temperature (sensor memory)")):
+                keep[k] = v
+        out[card] = keep
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_threads(cap: int = 16) -> int:
+    """Host threads for the CPU baseline: the cores this process may use,
+    at most `cap` (the host's share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
+def cpu_baseline(w, shard_rows: int, threads: int) -> dict:
+    """The oracle, as it stands, on the host's cores.  The fact table is cut
+    into `threads` shards of `shard_rows` consecutive rows; each shard runs the
+    whole plain pipeline (partition, filter, join with the full dimension
+    table, group-by, top-k) in the single-threaded C oracle, on its own host
+    thread, all shards at once.  Reported in the same unit as the GPU line
+    (algorithmic GB/s over the shards' rows), next to one shard alone on one
+    core.  The shards' partial groups are not merged (a merge of at most
+    threads x groups partial sums, left out of the timing)."""
+    import threading
+
     import torch
 
     import oracle
     import synth
-    spec = synth.FactSpec(sample_rows, w.fact.m, w.fact.seed)
-    fact = {k: v.numpy() for k, v in synth.fact_table(spec).items()}
-    dim = {k: v.numpy() for k, v in synth.dim_table(w.dim_m, w.dim_seed, w.attr_range).items()}
     oracle.lib()
+    dim = {k: v.numpy() for k, v in synth.dim_table(w.dim_m, w.dim_seed, w.attr_range).items()}
+    shards = []
+    for i in range(threads):
+        rows = torch.arange(i * shard_rows, (i + 1) * shard_rows, dtype=torch.int64)
+        shards.append({k: v.numpy() for k, v in synth.fact_columns(w.fact, rows).items()})
+
+    def pipeline(fact, out, idx):
+        pk, pcols, _, _ = oracle.partition(fact["fk"], w.log2_fanout,
+                                           [fact[c] for c in ("date", "qty", "price", "disc")])
+        pdate, pqty, pprice, pdisc = pcols
+        sel = oracle.filter(pdate, -(1 << 31), w.date_hi)
+        prow, pay = oracle.join(dim["key"], dim["attr"], pk, sel)
+        g = oracle.groupby(len(prow), pqty, pprice, pdisc, rowid=prow, key32=pay)
+        oracle.topk(pprice, 100, sel=sel)
+        out[idx] = sum(algorithmic_bytes(len(pk), w.dim_m, len(sel), len(g["count"]), 100).values())
+
+    one = [0]
     t0 = time.perf_counter()
-    pk, pcols, prow_id, poff = oracle.partition(fact["fk"], w.log2_fanout,
-                                                [fact[c] for c in ("date", "qty", "price", "disc")])
-    pdate, pqty, pprice, pdisc = pcols
-    sel = oracle.filter(pdate, -(1 << 31), w.date_hi)
-    prow, pay = oracle.join(dim["key"], dim["attr"], pk, sel)
-    g = oracle.groupby(len(prow), pqty, pprice, pdisc, rowid=prow, key32=pay)
-    oracle.topk(pprice, 100, sel=sel)
-    dt = time.perf_counter() - t0
-    by = algorithmic_bytes(sample_rows, w.dim_m, len(sel), len(g["count"]), 100)
-    return {"value": round(sum(by.values()) / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_rows:,} of {w.fact.n:,} fact rows with all {w.dim_m:,} dim rows; "
-                      f"same pipeline, single-threaded C oracle, {dt:.1f} s"}
+    pipeline(shards[0], one, 0)
+    dt1 = time.perf_counter() - t0
+    res = [0] * threads
+    ths = [threading.Thread(target=pipeline, args=(shards[i], res, i)) for i in range(threads)]
+    t0 = time.perf_counter()
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    dtn = time.perf_counter() - t0
+    return {"value": round(sum(res) / dtn / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{threads} shards of {shard_rows:,} consecutive fact rows ({threads * shard_rows:,} of "
+                      f"{w.fact.n:,}), each joined with all {w.dim_m:,} dim rows; the same pipeline in the "
+                      f"single-threaded C oracle, one host thread per shard, {dtn:.1f} s",
+            "single_core": {"value": round(one[0] / dt1 / 1e9, 3), "unit": "GB/s", "cores": 1,
+                            "sample": f"one shard of {shard_rows:,} rows, {dt1:.1f} s"}}
+
+
+def _timed(fn, steps, warm, stream):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _release():
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -124,15 +231,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=1, choices=[0, 1])
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "skew"],
-                    help="plain: the per-operator pipeline on one workload; "
-                         "batch: 512 join+aggregate instances, batched vs one launch chain each; "
-                         "serve: the served mix against serial execution; "
+                    help="plain: the per-operator pipeline on one workload, with the batched and served forms "
+                         "as sub-objects of its line; batch / serve: that form alone as the line; "
                          "skew: 100M Zipf(1.0) fact rows, composite-key group-by plus the 5%% pipeline")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-queries", type=int, default=160)
     ap.add_argument("--serve-rows", type=int, default=1_600_000_000)
     ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams of the served form")
-    ap.add_argument("--cpu-sample", type=int, default=33_554_432)
+    ap.add_argument("--no-batched", action="store_true", help="plain mode: leave out the batched sub-object")
+    ap.add_argument("--no-served", action="store_true", help="plain mode: leave out the served sub-object")
+    ap.add_argument("--cpu-shard-rows", type=int, default=0,
+                    help="rows per CPU-baseline shard (0: the fact rows split evenly over the threads)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0: the cores this process may use, at most 16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--probe", default="tune", choices=["tune", "auto", "ordered", "partitioned"],
@@ -150,22 +260,46 @@ def main():
                     help="also run a plain 1 GiB device copy (3 times) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU exchange is not built",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build runs the per-GPU hot path "
+              f"on one GPU's share; the multi-GPU exchange is not built", file=sys.stderr)
         sys.exit(2)
 
+    if args.mode == "batch":
+        out = bench_batch(args)
+        print(json.dumps(out), flush=True)
+        return
+    if args.mode == "serve":
+        out = bench_serve(args)
+        print(json.dumps(out), flush=True)
+        return
+    if args.mode == "skew":
+        return bench_skew(args)
+    clk0 = gpu_clocks()
+    out = bench_plain(args)
+    _release()
+    if args.workload == 1 and not args.no_batched:
+        out["batched"] = bench_batch(args, sub=True)
+        _release()
+    if args.workload == 1 and not args.no_served:
+        out["served"] = bench_serve(args, sub=True)
+        _release()
+    out["gpu_clocks"] = {"start": clk0, "end": gpu_clocks()}
+    if not args.no_cpu_baseline:
+        import synth
+        w = synth.workload(args.workload)
+        threads = args.cpu_threads or cpu_threads()
+        shard = min(args.cpu_shard_rows or w.fact.n, w.fact.n // threads)
+        out["cpu_baseline"] = cpu_baseline(w, shard, threads)
+    print(json.dumps(out), flush=True)
+
+
+def bench_plain(args) -> dict:
     import torch
 
     import synth
     import paper_2506_09226_amd as gq
     from paper_2506_09226_amd.pipeline import PlainPipeline
 
-    if args.mode == "batch":
-        return bench_batch(args)
-    if args.mode == "serve":
-        return bench_serve(args)
-    if args.mode == "skew":
-        return bench_skew(args)
     w = synth.workload(args.workload)
     torch.cuda.set_device(0)
     ctx = gq.Context(0)
@@ -221,7 +355,6 @@ def main():
     ctx.raise_status()
     print(f"# {args.steps} steps: {ms_step:.3f} ms/step (host wall {1e3 * wall / args.steps:.3f} ms/step)",
           file=sys.stderr, flush=True)
-
     by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100, partition=not args.no_partition)
     total_bytes = sum(by.values())
     kern = {}
@@ -275,10 +408,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, w.fact.n))
-    print(json.dumps(out), flush=True)
+    del pl, fact, dim
     ctx.close()
+    return out
 
 
 def bench_skew(args):
@@ -388,7 +520,10 @@ def batch_bytes(layout, sel_rows: int) -> int:
     return 28 * m + 4 * n + 48 * sel_rows
 
 
-def bench_batch(args):
+def bench_batch(args, sub: bool = False) -> dict:
+    """Batched workload: 512 join+aggregate instances in one persistent launch
+    (autotuned) against one plain launch chain per instance.  sub=True: the
+    object that the plain line carries as "batched"."""
     import numpy as np
     import torch
 
@@ -409,63 +544,50 @@ def bench_batch(args):
     by = batch_bytes(layout, sel_rows)
     stream = torch.cuda.current_stream()
 
-    def timed(fn, steps, warm):
-        for _ in range(warm):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(steps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
     b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
     tun, tune_ms = b.autotune(os.path.join(os.environ.get("TMPDIR", "/tmp"), "gq_batch_tuning.txt"))
     print(f"# autotuned: {tun.as_dict()} ({tune_ms:.2f} ms)", file=sys.stderr, flush=True)
-    ms_b = timed(b.run, args.steps, args.warmup)
+    ms_b = _timed(b.run, args.steps, args.warmup, stream)
     ctx.raise_status()
+    inst_ok = all(x == gq.GQ_OK for x in b.statuses())
     p = PlainPerInstance(ctx, cols, layout, 0, spec.date_hi)
-    ms_p = timed(p.run, max(1, args.steps // 2), 1)
+    ms_p = _timed(p.run, max(1, args.steps // 2), 1, stream)
     ctx.raise_status()
     rb, rp = b.results(), p.results()
-    same = True
+    same = inst_ok
     for x, y in zip(rb, rp):
         ox, oy = np.argsort(x["key32"]), np.argsort(y["key32"])
         for f in ("key32", "count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
             same &= bool(np.array_equal(x[f][ox], y[f][oy]))
-    out = {
-        "metric": METRIC,
-        "value": round(by / (ms_b * 1e6), 1),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_b, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": f"{len(layout)} join+aggregate instances, build log-uniform in [1e3, 2e6], "
-                               f"probe 8-16x build", "instances": len(layout),
-                   "build_rows": sum(l[1] for l in layout), "probe_rows": sum(l[3] for l in layout),
-                   "selected_rows": sel_rows, "form": "batched (one persistent launch)"},
-        "hbm_frac_of_peak": round(by / (ms_b * 1e6) / HBM_PEAK_GBS, 4),
-        "algorithmic_bytes_per_step": by,
-        "tuning": tun.as_dict(),
-        "plain_per_instance": {"ms_per_step": round(ms_p, 3), "GB/s": round(by / (ms_p * 1e6), 1),
-                               "launch_chains": len(layout)},
-        "speedup_vs_plain": round(ms_p / ms_b, 3),
-        "results_equal": same,
-    }
-    print(json.dumps(out), flush=True)
+    print(f"# batched {ms_b:.2f} ms, plain per instance {ms_p:.2f} ms", file=sys.stderr, flush=True)
+    workload = (f"{len(layout)} join+aggregate instances, build log-uniform in [1e3, 2e6], probe 8-16x build, "
+                f"date < {spec.date_hi}, group by dim attribute in [0, {spec.attr_range})")
+    res = {"workload": workload, "instances": len(layout), "build_rows": sum(l[1] for l in layout),
+           "probe_rows": sum(l[3] for l in layout), "selected_rows": sel_rows,
+           "form": "batched (one persistent launch, autotuned)", "steps": args.steps, "warmup": args.warmup,
+           "ms": round(ms_b, 4), "algorithmic_bytes": by, "GB/s": round(by / (ms_b * 1e6), 1),
+           "frac_of_peak": round(by / (ms_b * 1e6) / HBM_PEAK_GBS, 4), "tuning": tun.as_dict(),
+           "tuning_ms": round(tune_ms, 4),
+           "plain_per_instance": {"ms": round(ms_p, 3), "GB/s": round(by / (ms_p * 1e6), 1),
+                                  "launch_chains": len(layout), "steps": max(1, args.steps // 2)},
+           "speedup_vs_plain": round(ms_p / ms_b, 3), "results_equal": same}
+    del b, p, cols
     ctx.close()
+    if sub:
+        return res
+    return {"metric": METRIC, "value": res["GB/s"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": workload, "instances": len(layout), "build_rows": res["build_rows"],
+                       "probe_rows": res["probe_rows"], "selected_rows": sel_rows, "form": res["form"]},
+            "hbm_frac_of_peak": res["frac_of_peak"], "algorithmic_bytes_per_step": by, "tuning": res["tuning"],
+            "plain_per_instance": res["plain_per_instance"], "speedup_vs_plain": res["speedup_vs_plain"],
+            "results_equal": same}
 
 
-def bench_serve(args):
-    """Served mix vs serial plain execution under the same Poisson arrivals."""
+def bench_serve(args, sub: bool = False) -> dict:
+    """Served mix vs serial plain execution under the same Poisson arrivals.
+    sub=True: the object that the plain line carries as "served"."""
     import numpy as np
     import torch
 
@@ -506,11 +628,12 @@ def bench_serve(args):
             server.wait(s_)
         span = time.perf_counter() - t0
         lat = np.array([s_.latency for s_ in subs]) * 1e3
-        return subs, {"qps": round(len(subs) / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                      "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3)}
+        ok = all(s_.status == gq.GQ_OK for s_ in subs)
+        return subs, ok, {"qps": round(len(subs) / span, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3)}
 
     # serial service time: each query alone, one at a time
-    ser = Server(0, fact, t1, t2, pool, serial=True)
+    ser = Server(ctx, fact, t1, t2, pool, serial=True)
     warm = [ser.wait(ser.submit(q)) for q in qlist[:8]]
     iso = [ser.wait(ser.submit(q)).latency for q in qlist[:40]]
     t_bar = float(np.mean(iso))
@@ -519,50 +642,47 @@ def bench_serve(args):
     results_equal = True
     for load in (0.8, 1.5):
         arr = synth.poisson_arrivals(len(qlist), load / t_bar, spec.seed + int(load * 10))
-        subs_s, st_s = run(ser, arr)
-        srv = Server(0, fact, t1, t2, pool, streams=args.serve_streams, max_batch=16)
-        subs_b, st_b = run(srv, arr)
+        subs_s, ok_s, st_s = run(ser, arr)
+        srv = Server(ctx, fact, t1, t2, pool, streams=args.serve_streams, max_batch=16)
+        subs_b, ok_b, st_b = run(srv, arr)
         stats = srv.stats()
         srv.close()
+        results_equal &= ok_s and ok_b
         for a, b in zip(subs_s, subs_b):
             ra, rb = result_host(a), result_host(b)
             if a.spec.kind == gq.GQ_QUERY_FILTER_TOPK:
-                results_equal &= bool(np.array_equal(ra["row"], rb["row"]))
+                results_equal &= bool(np.array_equal(ra["row"], rb["row"]) and np.array_equal(ra["val"], rb["val"]))
             else:
                 key = "key64" if a.spec.kind == gq.GQ_QUERY_FILTER_AGG else "key32"
                 oa, ob = np.argsort(ra[key]), np.argsort(rb[key])
                 for f in (key, "count", "sum_qty", "sum_rev_lo", "sum_rev_hi"):
                     results_equal &= bool(np.array_equal(ra[f][oa], rb[f][ob]))
-        st_b.update({"batches": stats["batches"], "max_batch": stats["max_batch"]})
+        st_b.update({"batches": stats["batches"], "max_batch": stats["max_batch"], "reruns": stats["reruns"]})
         out_loads[f"{load}"] = {"offered_qps": round(load / t_bar, 2), "served": st_b, "serial": st_s}
         print(f"# load {load}: served {st_b} serial {st_s}", file=sys.stderr, flush=True)
     ser.close()
     main_load = out_loads["0.8"]
-    out = {
-        "metric": METRIC,
-        "value": main_load["served"]["qps"],
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": len(qlist),
-        "warmup": len(warm),
-        "ms_per_step": main_load["served"]["mean_ms"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": f"served mix over {spec.n:,} resident fact rows, dims {spec.m:,} rows each; "
-                               f"4 templates, selectivity U[1%,60%], Poisson arrivals",
-                   "resident_bytes": resident, "pool_bytes": pool.numel(), "queries": len(qlist),
-                   "form": f"served (continuous batching, shared scans, {args.serve_streams} streams)"},
-        "p50_ms": main_load["served"]["p50_ms"],
-        "p99_ms": main_load["served"]["p99_ms"],
-        "serial_service_ms": round(t_bar * 1e3, 3),
-        "loads": out_loads,
-        "results_equal": results_equal,
-    }
-    print(json.dumps(out), flush=True)
+    workload = (f"served mix over {spec.n:,} resident fact rows, two dims of {spec.m:,} rows; 4 templates "
+                f"(filter+agg, join+agg, two-join+agg, filter+top-100), selectivity U[1%,60%], Poisson arrivals "
+                f"at 0.8 and 1.5 / serial service time")
+    res = {"workload": workload, "resident_bytes": resident, "pool_bytes": pool.numel(), "queries": len(qlist),
+           "form": f"served (continuous batching, shared scans, {args.serve_streams} streams) vs serial plain",
+           "serial_service_ms": round(t_bar * 1e3, 3),
+           "p50_ms": main_load["served"]["p50_ms"], "p99_ms": main_load["served"]["p99_ms"],
+           "qps": main_load["served"]["qps"],
+           "serial_p50_ms": main_load["serial"]["p50_ms"], "serial_p99_ms": main_load["serial"]["p99_ms"],
+           "loads": out_loads, "results_equal": results_equal}
+    del pool, fact, t1, t2
     ctx.close()
+    if sub:
+        return res
+    return {"metric": METRIC, "value": res["qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(qlist),
+            "warmup": len(warm), "ms_per_step": main_load["served"]["mean_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": workload, "resident_bytes": resident, "pool_bytes": res["pool_bytes"],
+                       "queries": len(qlist), "form": res["form"]},
+            "p50_ms": res["p50_ms"], "p99_ms": res["p99_ms"], "serial_service_ms": res["serial_service_ms"],
+            "loads": out_loads, "results_equal": results_equal}
 
 
 if __name__ == "__main__":

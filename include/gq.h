@@ -56,6 +56,8 @@ typedef int32_t gq_status;
 #define GQ_ERR_HIP            5  /* a HIP runtime call failed                 */
 #define GQ_ERR_UNSUPPORTED    6  /* parameter outside the supported range     */
 #define GQ_ERR_INVALID_KEY    7  /* build key equal to the empty-slot marker  */
+#define GQ_ERR_TIMEOUT        8  /* a bounded device-side wait ran out (see
+                                    gq_set_wait_limit); outputs undefined     */
 
 /* Column element types; the value is the element width in bytes. */
 #define GQ_I32 4
@@ -81,11 +83,22 @@ void gq_ctx_destroy(gq_ctx *ctx);
 const char *gq_last_error(const gq_ctx *ctx);
 
 /* Synchronize `stream`, then read and clear the device status word: *out is
- * GQ_OK or the first device-side error recorded since the last read
- * (GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY, then
- * GQ_ERR_INVALID_ARG: a table whose header disagrees with its given size).
+ * GQ_OK or one device-side error recorded since the last read, the first
+ * present of GQ_ERR_TIMEOUT, GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY,
+ * GQ_ERR_CAPACITY, GQ_ERR_INVALID_ARG (a table whose header disagrees with
+ * its given size).
  * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
 gq_status gq_status_word(gq_ctx *ctx, gq_stream stream, gq_status *out);
+
+/* Bound of the device-side waits of kernels whose work items wait for
+ * other work items (the batched form's build and probe items): at most
+ * `polls` reads of the awaited counter, each after a short sleep.  polls = 0
+ * restores the default (2^24 polls, far beyond any wait of a correct run).
+ * A wait that runs out skips its item's work, raises GQ_ERR_TIMEOUT and lets
+ * the kernel finish its queue and exit; the affected outputs are undefined.
+ * A tiny bound (polls = 1) forces that path, for tests of the error
+ * handling.  Errors: GQ_ERR_INVALID_ARG (polls < 0). */
+gq_status gq_set_wait_limit(gq_ctx *ctx, int64_t polls);
 
 /* Per-kernel timing with HIP events recorded on the stream each kernel is
  * launched on (off by default).  gq_kernel_time synchronizes the device and
@@ -359,13 +372,22 @@ gq_tuning gq_default_tuning(void);
 size_t gq_batch_workspace_bytes(const gq_instance *inst, int n_inst, const gq_tuning *tuning);
 
 /* Run every instance of the host array inst[0..n_inst) in one persistent
- * kernel; tuning NULL = gq_default_tuning().  Each instance's out receives its
- * groups (unordered) and n_groups, exactly as gq_groupby_agg would.  ws must be
- * 256-byte aligned.  Device-side errors: GQ_ERR_DUPLICATE_KEY,
- * GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY.  Host errors: GQ_ERR_INVALID_ARG,
- * GQ_ERR_WORKSPACE. */
+ * kernel.  tuning NULL = gq_default_tuning() (autotuning is the separate,
+ * timed and cached gq_batch_autotune below, so that a plain call never
+ * spends seconds searching).  Each instance's out receives its groups
+ * (unordered) and n_groups, exactly as gq_groupby_agg would.  ws must be
+ * 256-byte aligned.
+ *   inst_status_dev  nullable device int32[n_inst]: receives, per instance,
+ *                    GQ_OK or that instance's own device-side error
+ *                    (GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY,
+ *                    GQ_ERR_CAPACITY, GQ_ERR_TIMEOUT; precedence as in
+ *                    gq_status_word).  An error of one instance leaves the
+ *                    other instances' outputs exact.
+ * Device-side errors of any instance are also recorded in the context's
+ * status word.  A foreign key equal to INT64_MIN (the empty-slot marker)
+ * matches no build key.  Host errors: GQ_ERR_INVALID_ARG, GQ_ERR_WORKSPACE. */
 gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, const gq_tuning *tuning,
-                            void *ws, size_t ws_bytes, gq_stream stream);
+                            gq_status *inst_status_dev, void *ws, size_t ws_bytes, gq_stream stream);
 
 /* Autotuner: times every candidate tuning (load factor x probe tile x lag) on
  * the given instances and returns the fastest in *best (its time in
@@ -432,9 +454,12 @@ typedef struct gq_query {
 
 typedef struct gq_server gq_server;
 
-/* Start a server on `device` (it creates its own context and a scheduler
- * thread).  Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
-gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out);
+/* Start a server on the device of `ctx` (the caller's context, which also
+ * receives the message of a failed create).  The server creates a scheduler
+ * thread and, per HIP stream, its own context, so that every batch in flight
+ * has its own device status word.
+ * Errors: GQ_ERR_INVALID_ARG, GQ_ERR_HIP. */
+gq_status gq_server_create(gq_ctx *ctx, const gq_server_cfg *cfg, gq_server **out);
 
 /* Queue a query; *ticket identifies it.  The query's output buffers must stay
  * valid until gq_server_wait returns for the ticket.  Thread-safe.
@@ -444,14 +469,25 @@ gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out
 gq_status gq_server_submit(gq_server *srv, const gq_query *q, uint64_t *ticket);
 
 /* Block until the query has finished on the device; *latency_s = seconds from
- * submit to completion; *query_status = GQ_OK or a launch error.  Each
- * ticket can be waited for once.  Thread-safe. */
+ * submit to completion (re-runs included); *query_status = the query's own
+ * result: GQ_OK, a launch error (GQ_ERR_HIP), or a device-side error of its
+ * kernels, read from its batch's status word when the batch retires
+ * (GQ_ERR_CAPACITY: more groups than its output capacity holds, the output
+ * then being undefined).  Error handling inside the server: a shared batch
+ * that reports an error runs each of its queries again alone, so that only
+ * the failing query reports it; a query whose groups overflow max_groups
+ * runs again with twice the bound, up to groups.capacity, so its status is
+ * GQ_ERR_CAPACITY only when the output arrays themselves are too small.  The
+ * caller's recovery is then to submit again with larger output arrays (and
+ * max_groups).  Each ticket can be waited for once.  Thread-safe. */
 gq_status gq_server_wait(gq_server *srv, uint64_t ticket, gq_status *query_status, double *latency_s);
 
-/* Counters: queries finished, batches launched, largest batch. */
-gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen);
+/* Counters: queries finished, batches launched, largest batch, queries run
+ * again after an error (any pointer may be NULL). */
+gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen,
+                          int64_t *reruns);
 
-/* Finish every queued query, stop the scheduler, release the context. */
+/* Finish every queued query, stop the scheduler, release its contexts. */
 void gq_server_destroy(gq_server *srv);
 
 #ifdef __cplusplus

@@ -26,13 +26,16 @@ GQ_ERR_DUPLICATE_KEY = 4
 GQ_ERR_HIP = 5
 GQ_ERR_UNSUPPORTED = 6
 GQ_ERR_INVALID_KEY = 7
+GQ_ERR_TIMEOUT = 8
 _NAMES = {0: "GQ_OK", 1: "GQ_ERR_INVALID_ARG", 2: "GQ_ERR_CAPACITY", 3: "GQ_ERR_WORKSPACE",
-          4: "GQ_ERR_DUPLICATE_KEY", 5: "GQ_ERR_HIP", 6: "GQ_ERR_UNSUPPORTED", 7: "GQ_ERR_INVALID_KEY"}
+          4: "GQ_ERR_DUPLICATE_KEY", 5: "GQ_ERR_HIP", 6: "GQ_ERR_UNSUPPORTED", 7: "GQ_ERR_INVALID_KEY",
+          8: "GQ_ERR_TIMEOUT"}
 
 GQ_I32, GQ_I64 = 4, 8
 
 EXPORTED = [
-    "gq_ctx_create", "gq_ctx_destroy", "gq_last_error", "gq_status_word", "gq_set_timing", "gq_kernel_time",
+    "gq_ctx_create", "gq_ctx_destroy", "gq_last_error", "gq_status_word", "gq_set_wait_limit", "gq_set_timing",
+    "gq_kernel_time",
     "gq_reset_timing", "gq_filter_workspace_bytes", "gq_filter", "gq_radix_partition_workspace_bytes",
     "gq_radix_partition", "gq_join_table_bytes", "gq_join_build_workspace_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
     "gq_join_probe_partitioned_workspace_bytes", "gq_join_probe_partitioned",
@@ -115,6 +118,8 @@ def lib():
         L.gq_last_error.argtypes = [vp]
         L.gq_status_word.restype = st
         L.gq_status_word.argtypes = [vp, vp, C.POINTER(C.c_int32)]
+        L.gq_set_wait_limit.restype = st
+        L.gq_set_wait_limit.argtypes = [vp, i64]
         L.gq_set_timing.restype = st
         L.gq_set_timing.argtypes = [vp, i32]
         L.gq_kernel_time.restype = st
@@ -156,20 +161,21 @@ def lib():
         L.gq_batch_workspace_bytes.restype = sz
         L.gq_batch_workspace_bytes.argtypes = [C.POINTER(Instance), i32, C.POINTER(Tuning)]
         L.gq_batch_join_agg.restype = st
-        L.gq_batch_join_agg.argtypes = [vp, C.POINTER(Instance), i32, C.POINTER(Tuning), vp, sz, vp]
+        L.gq_batch_join_agg.argtypes = [vp, C.POINTER(Instance), i32, C.POINTER(Tuning), vp, vp, sz, vp]
         L.gq_batch_autotune_workspace_bytes.restype = sz
         L.gq_batch_autotune_workspace_bytes.argtypes = [C.POINTER(Instance), i32]
         L.gq_batch_autotune.restype = st
         L.gq_batch_autotune.argtypes = [vp, C.POINTER(Instance), i32, C.c_char_p, C.POINTER(Tuning),
                                         C.POINTER(C.c_double), vp, sz, vp]
         L.gq_server_create.restype = st
-        L.gq_server_create.argtypes = [i32, C.POINTER(ServerCfg), C.POINTER(vp)]
+        L.gq_server_create.argtypes = [vp, C.POINTER(ServerCfg), C.POINTER(vp)]
         L.gq_server_submit.restype = st
         L.gq_server_submit.argtypes = [vp, C.POINTER(Query), C.POINTER(C.c_uint64)]
         L.gq_server_wait.restype = st
         L.gq_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.gq_server_stats.restype = st
-        L.gq_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.gq_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
         L.gq_server_destroy.restype = None
         L.gq_server_destroy.argtypes = [vp]
         _lib = L
@@ -239,6 +245,10 @@ class Context:
 
     def reset_timing(self):
         self.check(lib().gq_reset_timing(self.handle))
+
+    def set_wait_limit(self, polls: int):
+        """Bound of device-side waits in polls (0 = the default); see gq.h."""
+        self.check(lib().gq_set_wait_limit(self.handle, int(polls)))
 
     def workspace(self, nbytes: int) -> torch.Tensor:
         return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
@@ -424,15 +434,19 @@ def gq_default_tuning() -> Tuning:
     return lib().gq_default_tuning()
 
 
-def gq_batch_join_agg(ctx: Context, instances, tuning: Tuning | None = None, ws=None):
-    """Run all instances (a ctypes Instance array) in one persistent launch."""
+def gq_batch_join_agg(ctx: Context, instances, tuning: Tuning | None = None, ws=None, inst_status=None):
+    """Run all instances (a ctypes Instance array) in one persistent launch.
+    inst_status (optional device int32[n]) receives each instance's status."""
     n = len(instances)
     tp = C.byref(tuning) if tuning is not None else None
     need = lib().gq_batch_workspace_bytes(instances, n, tp)
     if need == 0:
         raise GQError(GQ_ERR_INVALID_ARG, "invalid batch or tuning")
     ws = ws if ws is not None else ctx.workspace(need)
-    ctx.check(lib().gq_batch_join_agg(ctx.handle, instances, n, tp, _ptr(ws), ws.numel(), _stream(ctx.device)))
+    if inst_status is not None and (inst_status.dtype != torch.int32 or inst_status.numel() < n):
+        raise ValueError("inst_status must be a device int32 tensor with one entry per instance")
+    ctx.check(lib().gq_batch_join_agg(ctx.handle, instances, n, tp, _ptr(inst_status), _ptr(ws), ws.numel(),
+                                      _stream(ctx.device)))
     return ws
 
 

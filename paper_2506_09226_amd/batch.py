@@ -27,6 +27,7 @@ class BatchedJoinAgg:
                           "qty": cols["qty"][no:no + n], "price": cols["price"][no:no + n],
                           "disc": cols["disc"][no:no + n], "date_lo": date_lo, "date_hi": date_hi, "out": out})
         self.instances = make_instances(specs)
+        self.inst_status = torch.zeros(len(layout), dtype=torch.int32, device=ctx.device)
         self.ws = None
         self.tuning = None
 
@@ -41,7 +42,11 @@ class BatchedJoinAgg:
             tp = byref(self.tuning) if self.tuning is not None else None
             need = lib().gq_batch_workspace_bytes(self.instances, len(self.instances), tp)
             self.ws = self.ctx.workspace(need)
-        gq_batch_join_agg(self.ctx, self.instances, self.tuning, ws=self.ws)
+        gq_batch_join_agg(self.ctx, self.instances, self.tuning, ws=self.ws, inst_status=self.inst_status)
+
+    def statuses(self):
+        """Each instance's status code of the last run (host list)."""
+        return self.inst_status.cpu().tolist()
 
     def results(self):
         return [o.host() for o in self.outs]

@@ -61,9 +61,17 @@ struct bt_inst {                   // device copy of one instance
     uint64_t *gcnt, *gsq, *glo;
     int64_t *ghi;
     uint64_t gmask;
-    uint32_t *counters;            // [0] init done, [1] build done, [2] probe done
+    uint32_t *counters;            // [0] init done, [1] build done, [2] probe done,
+                                   // [3] this instance's error bits (1 << gq_status)
     gq_groups out;
 };
+
+// An error of instance I: recorded in its own bits and in the context word.
+GQ_DEV void inst_raise(const bt_inst &I, uint32_t *status, int code)
+{
+    gq_raise(status, code);
+    gq_raise(&I.counters[3], code);
+}
 
 struct bt_seg {                    // a run of consecutive work items of one kind
     int64_t first_item;
@@ -76,11 +84,27 @@ GQ_DEV uint32_t load_acquire(const uint32_t *p)
     return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-GQ_DEV void wait_for(const uint32_t *ctr, uint32_t target)
+// Wait until *ctr >= target, for at most `limit` polls (each after a short
+// sleep).  Returns false, in every thread, when the bound ran out: the
+// caller then skips its work (its inputs are incomplete) and reports
+// GQ_ERR_TIMEOUT, so the kernel still drains its queue and exits.  Every
+// wait here is for items dequeued earlier, so the bound is only reached
+// through a bug, or when the host sets a tiny bound to test this path.
+GQ_DEV bool wait_for(const uint32_t *ctr, uint32_t target, int64_t limit, uint32_t *s_ok)
 {
-    if (threadIdx.x == 0)
-        while (load_acquire(ctr) < target) __builtin_amdgcn_s_sleep(2);
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        for (int64_t polls = 0; load_acquire(ctr) < target; ++polls) {
+            if (polls >= limit) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_ok = ok;
+    }
     __syncthreads();
+    return gq_uniform(*s_ok) != 0;
 }
 
 GQ_DEV void signal_done(uint32_t *ctr)
@@ -198,7 +222,7 @@ GQ_DEV int64_t global_group(const bt_inst &I, bool active, int32_t key, uint32_t
                     found = static_cast<int64_t>(s);
                     done = true;
                 } else if (++probes > I.gmask) {
-                    gq_raise(status, GQ_ERR_CAPACITY);
+                    inst_raise(I, status, GQ_ERR_CAPACITY);
                     done = true;
                 } else {
                     s = (s + 1) & I.gmask;
@@ -229,7 +253,7 @@ __device__ void item_lds_build(const bt_inst &I, uint32_t *status, unsigned long
     for (int64_t i = threadIdx.x; i < I.m; i += BT_THREADS) {
         const int64_t k = I.dim_key[i];
         if (k == BT_EMPTY) {
-            gq_raise(status, GQ_ERR_INVALID_KEY);
+            inst_raise(I, status, GQ_ERR_INVALID_KEY);
             continue;
         }
         uint32_t s = static_cast<uint32_t>(key_hash(k) >> (64 - L));
@@ -241,7 +265,7 @@ __device__ void item_lds_build(const bt_inst &I, uint32_t *status, unsigned long
                 break;
             }
             if (prev == static_cast<unsigned long long>(k)) {
-                gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                inst_raise(I, status, GQ_ERR_DUPLICATE_KEY);
                 break;
             }
             s = (s + 1) & (S - 1);
@@ -296,7 +320,7 @@ __device__ void item_build(const bt_inst &I, int64_t tile, int build_tile, uint3
 #pragma unroll
         for (int c = 0; c < BT_BUILD_ITEMS; ++c) {
             if (valid[c] && k[c] == BT_EMPTY) {
-                gq_raise(status, GQ_ERR_INVALID_KEY);
+                inst_raise(I, status, GQ_ERR_INVALID_KEY);
                 valid[c] = false;
             }
             s[c] = key_hash(k[c]) >> (64 - L);
@@ -315,11 +339,11 @@ __device__ void item_build(const bt_inst &I, int64_t tile, int build_tile, uint3
                     break;
                 }
                 if (prev[c] == static_cast<unsigned long long>(k[c])) {
-                    gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                    inst_raise(I, status, GQ_ERR_DUPLICATE_KEY);
                     break;
                 }
                 if (++p > mask) {
-                    gq_raise(status, GQ_ERR_CAPACITY);
+                    inst_raise(I, status, GQ_ERR_CAPACITY);
                     break;
                 }
                 s[c] = (s[c] + 1) & mask;
@@ -360,6 +384,7 @@ __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds
         for (int c = 0; c < BT_CHUNK_ITEMS; ++c) {
             const int64_t r = base + c * BT_THREADS + threadIdx.x;
             k[c] = pass[c] ? I.fk[r] : BT_EMPTY;
+            pass[c] = pass[c] && k[c] != BT_EMPTY;      // the empty-slot marker is no key: it never matches
         }
         uint64_t s[BT_CHUNK_ITEMS];
         int4 v[BT_CHUNK_ITEMS];
@@ -433,7 +458,7 @@ __device__ void emit_groups(const bt_inst &I, uint32_t *status)
         if (occ) {
             const int64_t idx = static_cast<int64_t>(base + gq_mbcnt(mk));
             if (idx >= I.out.capacity) {
-                gq_raise(status, GQ_ERR_CAPACITY);
+                inst_raise(I, status, GQ_ERR_CAPACITY);
                 continue;
             }
             const uint64_t cnt = __hip_atomic_load(&I.gcnt[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -457,7 +482,8 @@ __device__ void emit_groups(const bt_inst &I, uint32_t *status)
 __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const bt_inst *__restrict__ insts,
                                                            const bt_seg *__restrict__ segs, int nsegs,
                                                            int64_t total_items, uint32_t *work_ctr, int init_tile,
-                                                           int build_tile, int probe_tile, uint32_t *status)
+                                                           int build_tile, int probe_tile, int64_t wait_limit,
+                                                           uint32_t *status)
 {
     // one LDS buffer serves either use: the probe aggregation table or the
     // region copy of a table being built (never both within one item)
@@ -468,7 +494,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const bt_inst *__rest
     unsigned long long *sk = reinterpret_cast<unsigned long long *>(lds_buf);
     int32_t *sp = reinterpret_cast<int32_t *>(lds_buf + BT_REGION_SLOTS * sizeof(unsigned long long));
     __shared__ int64_t s_item;
-    __shared__ uint32_t s_last;
+    __shared__ uint32_t s_last, s_ok;
     // Each pass starts with a barrier that every thread executes, so the
     // thread-0 dequeue below is never fused with the thread-0 tail of the
     // previous item (signal_done): fused, the two would form one divergent
@@ -496,12 +522,16 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const bt_inst *__rest
             item_init(I, tile, init_tile);
             signal_done(&I.counters[0]);
         } else if (sg.kind == K_BUILD) {
-            wait_for(&I.counters[0], static_cast<uint32_t>(I.init_items));
-            item_build(I, tile, build_tile, status);
+            if (wait_for(&I.counters[0], static_cast<uint32_t>(I.init_items), wait_limit, &s_ok))
+                item_build(I, tile, build_tile, status);
+            else if (threadIdx.x == 0)
+                inst_raise(I, status, GQ_ERR_TIMEOUT);
             signal_done(&I.counters[1]);
         } else {
-            wait_for(&I.counters[1], static_cast<uint32_t>(I.build_items));
-            item_probe(I, tile, probe_tile, T, status);
+            if (wait_for(&I.counters[1], static_cast<uint32_t>(I.build_items), wait_limit, &s_ok))
+                item_probe(I, tile, probe_tile, T, status);
+            else if (threadIdx.x == 0)
+                inst_raise(I, status, GQ_ERR_TIMEOUT);
             __syncthreads();
             if (threadIdx.x == 0) {
                 __threadfence();
@@ -523,6 +553,14 @@ __global__ void batch_zero_counts_kernel(const bt_inst *insts, int n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         *insts[i].out.n_groups = 0;
+}
+
+// Each instance's error bits as one status code (the same precedence as the
+// context's status word), once the batch kernel has finished.
+__global__ void batch_status_kernel(const bt_inst *insts, int n, int32_t *inst_status)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        inst_status[i] = gq_status_of_bits(insts[i].counters[3]);
 }
 
 }  // namespace
@@ -660,8 +698,8 @@ size_t gq_batch_workspace_bytes(const gq_instance *inst, int n_inst, const gq_tu
     return make_plan(inst, n_inst, t, nullptr).bytes;
 }
 
-gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, const gq_tuning *tuning, void *ws,
-                            size_t ws_bytes, gq_stream stream)
+gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, const gq_tuning *tuning,
+                            gq_status *inst_status_dev, void *ws, size_t ws_bytes, gq_stream stream)
 {
     if (!ctx) return GQ_ERR_INVALID_ARG;
     if (!inst || n_inst < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_batch_join_agg: no instances");
@@ -695,13 +733,18 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
                                          hipMemcpyHostToDevice, s));
     GQ_TRY(gq_launch(ctx, "gq_batch_zero", batch_zero_counts_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, s,
                      static_cast<const bt_inst *>(d_insts), n_inst));
-    if (pl.total_items == 0) return GQ_OK;
-    // three 48 KiB-LDS workgroups fit a CU
-    const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(pl.total_items, int64_t(ctx->num_cus) * 3));
-    const int nsegs = static_cast<int>(pl.segs.size());
-    return gq_launch(ctx, "gq_batch", batch_kernel, dim3(grid), dim3(BT_THREADS), 0, s,
-                     static_cast<const bt_inst *>(d_insts), static_cast<const bt_seg *>(d_segs), nsegs,
-                     pl.total_items, work, t.init_tile, t.build_tile, t.probe_tile, ctx->status_dev);
+    if (pl.total_items > 0) {
+        // three 48 KiB-LDS workgroups fit a CU
+        const uint32_t grid = static_cast<uint32_t>(std::min<int64_t>(pl.total_items, int64_t(ctx->num_cus) * 3));
+        const int nsegs = static_cast<int>(pl.segs.size());
+        GQ_TRY(gq_launch(ctx, "gq_batch", batch_kernel, dim3(grid), dim3(BT_THREADS), 0, s,
+                         static_cast<const bt_inst *>(d_insts), static_cast<const bt_seg *>(d_segs), nsegs,
+                         pl.total_items, work, t.init_tile, t.build_tile, t.probe_tile, ctx->wait_limit,
+                         ctx->status_dev));
+    }
+    if (!inst_status_dev) return GQ_OK;
+    return gq_launch(ctx, "gq_batch_status", batch_status_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, s,
+                     static_cast<const bt_inst *>(d_insts), n_inst, static_cast<int32_t *>(inst_status_dev));
 }
 
 }  // extern "C"
@@ -714,13 +757,24 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
 // --------------------------------------------------------------------------
 namespace {
 
-uint64_t batch_signature(const gq_instance *in, int n)
+// What the fastest tuning depends on: the device (compute units, LDS) and,
+// per instance, the table and probe sizes, the filter range and the group
+// capacity (which sizes the group tables).
+uint64_t batch_signature(const gq_ctx *ctx, const gq_instance *in, int n)
 {
     uint64_t h = 0x9E3779B97F4A7C15ull ^ static_cast<uint64_t>(n);
-    for (int i = 0; i < n; ++i) {
-        h = (h ^ static_cast<uint64_t>(in[i].m)) * 0xff51afd7ed558ccdull;
-        h = (h ^ static_cast<uint64_t>(in[i].n)) * 0xc4ceb9fe1a85ec53ull;
+    auto mix = [&h](uint64_t v) {
+        h = (h ^ v) * 0xff51afd7ed558ccdull;
         h ^= h >> 29;
+    };
+    mix(static_cast<uint64_t>(ctx->num_cus));
+    mix(static_cast<uint64_t>(ctx->lds_per_cu));
+    for (int i = 0; i < n; ++i) {
+        mix(static_cast<uint64_t>(in[i].m));
+        mix(static_cast<uint64_t>(in[i].n));
+        mix(static_cast<uint64_t>(in[i].date_lo));
+        mix(static_cast<uint64_t>(in[i].date_hi));
+        mix(static_cast<uint64_t>(in[i].out.capacity));
     }
     return h;
 }
@@ -791,7 +845,8 @@ gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
                             gq_tuning *best, double *best_ms, void *ws, size_t ws_bytes, gq_stream stream)
 {
     if (!ctx || !best || !best_ms) return GQ_ERR_INVALID_ARG;
-    const uint64_t sig = batch_signature(inst, n_inst);
+    if (!inst || n_inst < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_batch_autotune: no instances");
+    const uint64_t sig = batch_signature(ctx, inst, n_inst);
     if (cache_lookup(cache_path, sig, best, best_ms)) return GQ_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
@@ -801,10 +856,10 @@ gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
     gq_tuning bt = gq_default_tuning();
     gq_status rc = GQ_OK;
     for (const gq_tuning &t : candidates()) {
-        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, ws, ws_bytes, stream);            // warm-up
+        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream);   // warm-up
         if (rc != GQ_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { rc = GQ_ERR_HIP; break; }
-        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, ws, ws_bytes, stream);
+        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream);
         if (rc != GQ_OK) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = GQ_ERR_HIP; break; }
         float ms = 0.f;

@@ -23,6 +23,17 @@ GQ_DEV uint64_t gq_fmix64(uint64_t k)
 // Status-word bits set by kernels (bit = 1 << gq_status code).
 GQ_DEV void gq_raise(uint32_t *status, int code) { atomicOr(status, 1u << code); }
 
+// The status code reported for a set of error bits: the first present of
+// timeout, duplicate key, invalid key, capacity, invalid argument (codes of
+// gq.h), else 0 (GQ_OK).
+__host__ __device__ inline int32_t gq_status_of_bits(uint32_t bits)
+{
+    const int32_t order[] = {8, 4, 7, 2, 1};
+    for (int32_t c : order)
+        if (bits & (1u << c)) return c;
+    return 0;
+}
+
 GQ_DEV int gq_lane() { return __lane_id(); }
 
 // Number of set bits of `mask` in lanes below the calling lane.

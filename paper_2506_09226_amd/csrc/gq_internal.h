@@ -23,6 +23,7 @@ struct gq_ctx {
     int num_cus = 256;
     size_t lds_per_cu = 160 * 1024;
     uint32_t *status_dev = nullptr;          // bit (1 << code) per device error
+    int64_t wait_limit = int64_t(1) << 24;   // polls of a bounded device-side wait
     std::string last_error;
     bool timing = false;
     std::vector<gq_timing_rec> pending;      // recorded, not yet collected

@@ -1146,11 +1146,17 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
         GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_wide_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0,
                          s, a, pl.P, pl.chunk_rows, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
                          w.side_cnt));
-    else
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>,
-                         dim3(static_cast<uint32_t>(std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3)))), dim3(GB_THREADS), 0, s,
-                         a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side, w.side_cnt,
-                         w.side_cnt + 32));
+    else {
+        // XCD x scatters the x-th eighth of the tiles with the workgroups b of
+        // b mod 8 = x, so the grid is a whole number of rounds over the eight
+        // XCDs (at least one workgroup each, even for fewer than 8 tiles); a
+        // workgroup whose range is empty exits at once
+        int64_t sgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3));
+        sgrid = (sgrid + GQ_NUM_XCD - 1) / GQ_NUM_XCD * GQ_NUM_XCD;
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(static_cast<uint32_t>(sgrid)),
+                         dim3(GB_THREADS), 0, s, a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
+                         w.side_cnt, w.side_cnt + 32));
+    }
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));

@@ -99,17 +99,18 @@ gq_status gq_status_word(gq_ctx *ctx, gq_stream stream, gq_status *out)
     uint32_t bits = 0;
     GQ_CHECK_HIP(ctx, hipMemcpyAsync(&bits, ctx->status_dev, sizeof bits, hipMemcpyDeviceToHost, s));
     GQ_CHECK_HIP(ctx, hipStreamSynchronize(s));
-    *out = GQ_OK;
-    const int order[] = {GQ_ERR_DUPLICATE_KEY, GQ_ERR_INVALID_KEY, GQ_ERR_CAPACITY, GQ_ERR_INVALID_ARG};
-    for (int c : order)
-        if (bits & (1u << c)) {
-            *out = c;
-            break;
-        }
+    *out = gq_status_of_bits(bits);
     if (bits) {
         GQ_TRY(gq_zero(ctx, ctx->status_dev, 1, s));
         GQ_CHECK_HIP(ctx, hipStreamSynchronize(s));
     }
+    return GQ_OK;
+}
+
+gq_status gq_set_wait_limit(gq_ctx *ctx, int64_t polls)
+{
+    if (!ctx || polls < 0) return GQ_ERR_INVALID_ARG;
+    ctx->wait_limit = polls == 0 ? (int64_t(1) << 24) : polls - 1;
     return GQ_OK;
 }
 

@@ -39,6 +39,7 @@ struct sv_table {                                     // view of a join table bu
 
 GQ_DEV bool sv_lookup(const sv_table &t, int64_t k, int32_t &payload)
 {
+    if (k == SV_EMPTY) return false;                  // the empty-slot marker is no key: it never matches
     const uint64_t mask = (1ull << t.L) - 1;
     uint64_t s = gq_fmix64(static_cast<uint64_t>(k)) >> (64 - t.L);
     for (uint64_t p = 0; p <= mask; ++p) {
@@ -149,6 +150,10 @@ GQ_DEV void global_add(const sv_gtable &g, int64_t s, uint64_t cnt, uint64_t sq,
     add128(&g.lo[s], &g.hi[s], rev);
 }
 
+struct sv_outs {                      // output descriptors of a batch's queries, passed by value
+    gq_serve_query_out o[SV_MAX_BATCH];
+};
+
 struct sv_batch {                     // kernel view of a batch
     int nq;
     int64_t hi[SV_MAX_BATCH];         // date_hi per level, descending
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_agg_kernel(gq_serve_tables t, s
 // merged in an LDS table and written to that query's output.
 constexpr int SV_EMIT_SLOTS = 2 * SV_MAX_AGG_GROUPS;
 
-__global__ __launch_bounds__(256) void sv_emit_kernel(sv_batch b, gq_serve_query_out *outs, uint32_t *status)
+__global__ __launch_bounds__(256) void sv_emit_kernel(sv_batch b, sv_outs outs, uint32_t *status)
 {
     __shared__ uint32_t st[SV_EMIT_SLOTS];
     __shared__ int64_t ky[SV_EMIT_SLOTS];
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(256) void sv_emit_kernel(sv_batch b, gq_serve_query
     for (int i = 0; i < PER; ++i) mine += st[threadIdx.x * PER + i] == 2u ? 1u : 0u;
     uint32_t total;
     uint32_t idx = gq_block_exclusive_scan<256>(mine, &total, scan_smem);
-    const gq_groups &out = outs[b.qidx[l]].groups;
+    const gq_groups &out = outs.o[b.qidx[l]].groups;
     for (int i = 0; i < PER; ++i) {
         const int s = threadIdx.x * PER + i;
         if (st[s] != 2u) continue;
@@ -328,12 +333,12 @@ __global__ __launch_bounds__(256) void sv_emit_kernel(sv_batch b, gq_serve_query
     if (threadIdx.x == 0) *out.n_groups = total;
 }
 
-__global__ void sv_zero_counts_kernel(gq_serve_query_out *outs, int nq, int topk)
+__global__ void sv_zero_counts_kernel(sv_outs outs, int nq, int topk)
 {
     const int q = threadIdx.x;
     if (q >= nq) return;
-    if (topk) *outs[q].topk_n = 0;
-    else *outs[q].groups.n_groups = 0;
+    if (topk) *outs.o[q].topk_n = 0;
+    else *outs.o[q].groups.n_groups = 0;
 }
 
 // ------------------------------------------------------------ top-k batch
@@ -445,7 +450,7 @@ __global__ __launch_bounds__(SV_THREADS) void sv_topk_local_kernel(gq_serve_tabl
 // Stage 2: block q merges query q's candidates from every stage-1 block.
 __global__ __launch_bounds__(SV_THREADS) void sv_topk_merge_kernel(const uint64_t *cand_ok, const uint32_t *cand_rk,
                                                                    const uint32_t *cand_cnt, int nblocks, int k,
-                                                                   gq_serve_query_out *outs)
+                                                                   sv_outs outs)
 {
     __shared__ sv_tk_lds L;                                  // uses slot 0 only
     const int q = blockIdx.x;
@@ -480,10 +485,10 @@ __global__ __launch_bounds__(SV_THREADS) void sv_topk_merge_kernel(const uint64_
     tk_compact(L, 0, k);
     const uint32_t c = L.count[0] < static_cast<uint32_t>(k) ? L.count[0] : static_cast<uint32_t>(k);
     for (uint32_t i = threadIdx.x; i < c; i += SV_THREADS) {
-        outs[q].topk_val[i] = static_cast<int64_t>(L.ok[0][i] ^ 0x8000000000000000ull);
-        outs[q].topk_row[i] = static_cast<int32_t>(0x7fffffffu - L.rk[0][i]);
+        outs.o[q].topk_val[i] = static_cast<int64_t>(L.ok[0][i] ^ 0x8000000000000000ull);
+        outs.o[q].topk_row[i] = static_cast<int32_t>(0x7fffffffu - L.rk[0][i]);
     }
-    if (threadIdx.x == 0) *outs[q].topk_n = c;
+    if (threadIdx.x == 0) *outs.o[q].topk_n = c;
 }
 
 uint64_t pow2_at_least(uint64_t x)
@@ -511,7 +516,6 @@ size_t gq_serve_batch_bytes(const gq_serve_tables &t, const gq_serve_query *q, i
 {
     if (nq < 1) return 0;
     gq_carver c(nullptr);
-    c.take<gq_serve_query_out>(SV_MAX_BATCH);
     const int kind = q[0].kind;
     if (kind == GQ_QUERY_FILTER_AGG || kind == GQ_QUERY_JOIN2_AGG) {
         for (int i = 0; i < nq; ++i) {
@@ -543,13 +547,11 @@ size_t gq_serve_batch_bytes(const gq_serve_tables &t, const gq_serve_query *q, i
     return c.bytes();
 }
 
-static gq_status copy_outs(gq_ctx *ctx, gq_serve_query_out *d_outs, const gq_serve_query *q, int nq,
-                           hipStream_t s)
+static sv_outs outs_of(const gq_serve_query *q, int nq)
 {
-    gq_serve_query_out h[SV_MAX_BATCH];
-    for (int i = 0; i < nq; ++i) h[i] = q[i].out;
-    GQ_CHECK_HIP(ctx, hipMemcpyAsync(d_outs, h, sizeof(gq_serve_query_out) * nq, hipMemcpyHostToDevice, s));
-    return GQ_OK;
+    sv_outs o{};
+    for (int i = 0; i < nq; ++i) o.o[i] = q[i].out;
+    return o;
 }
 
 gq_status gq_serve_batch(gq_ctx *ctx, const gq_serve_tables &t, const gq_serve_query *q, int nq, void *ws,
@@ -561,8 +563,7 @@ gq_status gq_serve_batch(gq_ctx *ctx, const gq_serve_tables &t, const gq_serve_q
         if (q[i].kind != kind) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "serve batch mixes templates");
     if (ws_bytes < gq_serve_batch_bytes(t, q, nq)) return gq_fail(ctx, GQ_ERR_WORKSPACE, "serve batch workspace");
     gq_carver c(ws);
-    gq_serve_query_out *d_outs = c.take<gq_serve_query_out>(SV_MAX_BATCH);
-    GQ_TRY(copy_outs(ctx, d_outs, q, nq, s));
+    const sv_outs d_outs = outs_of(q, nq);
     int64_t max_hi = INT32_MIN;
     for (int i = 0; i < nq; ++i) max_hi = std::max(max_hi, q[i].date_hi);
     // three 40 KiB-LDS workgroups per CU; a persistent grid-stride loop over the rows

@@ -1,6 +1,14 @@
 // Request loop of the served form: footprint admission, continuous batching
 // of same-template queries into shared scans, batches in flight on several
-// HIP streams, completion by event polling, per-query latency.
+// HIP streams, completion by event polling, per-query latency and status.
+//
+// Errors.  Each stream slot has its own context, so its own device status
+// word; the word is copied to pinned host memory at the end of every batch
+// and read when the batch retires.  A batch of several queries that reports
+// an error is not charged to all of them: each query is run again alone.  A
+// query alone that overflows its group table (GQ_ERR_CAPACITY) is run again
+// with twice the group bound, up to its output capacity; past that, the
+// query reports GQ_ERR_CAPACITY (the caller may retry with larger outputs).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,6 +21,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "gq_device.h"
 #include "gq_internal.h"
 #include "gq_serve.h"
 
@@ -24,6 +33,7 @@ struct pending {
     uint64_t ticket;
     gq_serve_query q;
     clk::time_point submitted;
+    bool solo = false;                    // run alone (a re-run after a batch error)
 };
 
 struct done_state {
@@ -34,10 +44,12 @@ struct done_state {
 };
 
 struct slot_t {
+    gq_ctx *ctx = nullptr;                // its own device status word
+    uint32_t *status_host = nullptr;      // pinned copy of that word, per batch
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    std::vector<uint64_t> tickets;
+    std::vector<pending> items;
     size_t off = 0, bytes = 0;
     gq_status launch_status = GQ_OK;
 };
@@ -82,7 +94,6 @@ struct pool_alloc {
 
 struct gq_server {
     int device = 0;
-    gq_ctx *ctx = nullptr;
     gq_serve_tables tables{};
     char *pool = nullptr;
     size_t pool_bytes = 0;
@@ -97,7 +108,7 @@ struct gq_server {
     std::thread th;
     bool stop = false;
     uint64_t next_ticket = 1;
-    int64_t n_done = 0, n_batches = 0, max_seen = 0;
+    int64_t n_done = 0, n_batches = 0, max_seen = 0, n_reruns = 0;
 
     // A shared scan pays for itself only from a few queries of one template
     // on (measured on MI355X over 1.6 billion rows): with fewer queued, the
@@ -119,17 +130,65 @@ struct gq_server {
         for (int i = 0; i < nq; ++i) b = std::max(b, gq_serve_single_bytes(tables, q[i]));
         return b;
     }
-    gq_status run(const gq_serve_query *q, int nq, void *ws, size_t bytes, hipStream_t s)
+    // Launch a batch on slot sl: its operators, then a copy of the slot's
+    // status word to pinned memory and a clear of the word, all on its stream.
+    gq_status run(slot_t &sl, const gq_serve_query *q, int nq, void *ws, size_t bytes)
     {
-        if (shared(q, nq)) return gq_serve_batch(ctx, tables, q, nq, ws, bytes, s);
-        for (int i = 0; i < nq; ++i) {           // (one query, unless the pool cut a shared batch short)
-            const gq_status st = gq_serve_single(ctx, tables, q[i], ws, bytes, s);
-            if (st != GQ_OK) return st;
+        gq_status st = GQ_OK;
+        if (shared(q, nq)) {
+            st = gq_serve_batch(sl.ctx, tables, q, nq, ws, bytes, sl.stream);
+        } else {
+            for (int i = 0; i < nq && st == GQ_OK; ++i)   // (one query, unless the pool cut a shared batch short)
+                st = gq_serve_single(sl.ctx, tables, q[i], ws, bytes, sl.stream);
         }
-        return GQ_OK;
+        if (hipMemcpyAsync(sl.status_host, sl.ctx->status_dev, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           sl.stream) != hipSuccess && st == GQ_OK)
+            st = GQ_ERR_HIP;
+        const gq_status z = gq_zero(sl.ctx, sl.ctx->status_dev, 1, sl.stream);
+        return st != GQ_OK ? st : z;
     }
+    void retire(slot_t &sl, hipError_t q);
     void loop();
 };
+
+// A finished batch: its queries complete, or go back to the head of the
+// queue to run again alone (see the error policy at the top of the file).
+void gq_server::retire(slot_t &sl, hipError_t q)
+{
+    gq_status st = sl.launch_status;
+    if (st == GQ_OK) st = q == hipSuccess ? gq_status_of_bits(*sl.status_host) : GQ_ERR_HIP;
+    std::vector<pending> again;
+    const auto now = clk::now();
+    for (pending &p : sl.items) {
+        const bool agg = p.q.kind != GQ_QUERY_FILTER_TOPK;
+        if (st != GQ_OK && st != GQ_ERR_HIP && sl.items.size() > 1) {
+            p.solo = true;                       // whose error was it? run each alone
+            again.push_back(p);
+            continue;
+        }
+        if (st == GQ_ERR_CAPACITY && agg && p.q.max_groups < p.q.out.groups.capacity) {
+            gq_serve_query x = p.q;
+            x.max_groups = std::min<int64_t>(2 * x.max_groups, x.out.groups.capacity);
+            if (((gq_serve_single_bytes(tables, x) + 255) & ~size_t(255)) <= (pool_bytes & ~size_t(255))) {
+                p.q = x;                         // it still fits the pool alone: run it again, larger
+                p.solo = true;
+                again.push_back(p);
+                continue;
+            }
+        }
+        done_state &d = states[p.ticket];
+        d.done = true;
+        d.status = st;
+        d.latency = std::chrono::duration<double>(now - d.submitted).count();
+        ++n_done;
+    }
+    for (size_t i = again.size(); i-- > 0;) queue.push_front(again[i]);
+    n_reruns += static_cast<int64_t>(again.size());
+    alloc.give(sl.off, sl.bytes);
+    sl.busy = false;
+    sl.items.clear();
+    cv_done.notify_all();
+}
 
 void gq_server::loop()
 {
@@ -137,25 +196,13 @@ void gq_server::loop()
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         bool progress = false;
-        // retire finished batches
+        // retire finished batches (a failed batch still retires)
         for (auto &sl : slots) {
             if (!sl.busy) continue;
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
-            const gq_status st = q == hipSuccess ? sl.launch_status : GQ_ERR_HIP;   // a failed batch still retires
-            const auto now = clk::now();
-            for (uint64_t t : sl.tickets) {
-                done_state &d = states[t];
-                d.done = true;
-                d.status = st;
-                d.latency = std::chrono::duration<double>(now - d.submitted).count();
-                ++n_done;
-            }
-            alloc.give(sl.off, sl.bytes);
-            sl.busy = false;
-            sl.tickets.clear();
+            retire(sl, q);
             progress = true;
-            cv_done.notify_all();
         }
         // admit and launch
         bool any_busy = false;
@@ -171,10 +218,13 @@ void gq_server::loop()
             if (h == queue.size()) continue;
             std::vector<size_t> pick;                     // indices into queue
             const gq_serve_query head = queue[h].q;
-            const int limit = serial ? 1 : max_batch;
+            const int limit = (serial || queue[h].solo) ? 1 : max_batch;
             for (size_t i = h; i < queue.size() && static_cast<int>(pick.size()) < limit; ++i) {
                 const gq_serve_query &x = queue[i].q;
-                if (x.kind == head.kind && (x.kind != GQ_QUERY_FILTER_TOPK || x.k == head.k)) pick.push_back(i);
+                if (x.kind == head.kind && !queue[i].solo && (x.kind != GQ_QUERY_FILTER_TOPK || x.k == head.k))
+                    pick.push_back(i);
+                else if (i == h)
+                    pick.push_back(i);                    // a solo head runs by itself
             }
             if (head.kind == GQ_QUERY_FILTER_TOPK && pick.size() > 8) pick.resize(8);
             if (static_cast<int>(pick.size()) < min_shared(head.kind)) pick.resize(1);   // no shared scan: one query
@@ -188,20 +238,18 @@ void gq_server::loop()
                 pick.pop_back();
             }
             if (pick.empty()) break;                       // wait for memory to free up
-            std::vector<uint64_t> tickets;
-            for (size_t k = pick.size(); k-- > 0;) {
-                tickets.push_back(queue[pick[k]].ticket);
-                queue.erase(queue.begin() + static_cast<long>(pick[k]));
-            }
+            std::vector<pending> items;
+            for (size_t i : pick) items.push_back(queue[i]);
+            for (size_t k = pick.size(); k-- > 0;) queue.erase(queue.begin() + static_cast<long>(pick[k]));
             sl.busy = true;
             any_busy = true;
-            sl.tickets = tickets;
+            sl.items = items;
             sl.off = off;
             sl.bytes = bytes;
             ++n_batches;
             if (static_cast<int64_t>(qs.size()) > max_seen) max_seen = static_cast<int64_t>(qs.size());
             lk.unlock();
-            gq_status st = run(qs.data(), static_cast<int>(qs.size()), pool + off, bytes, sl.stream);
+            gq_status st = run(sl, qs.data(), static_cast<int>(qs.size()), pool + off, bytes);
             if (hipEventRecord(sl.done, sl.stream) != hipSuccess && st == GQ_OK) st = GQ_ERR_HIP;
             lk.lock();
             sl.launch_status = st;
@@ -217,22 +265,19 @@ void gq_server::loop()
 
 extern "C" {
 
-gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out)
+gq_status gq_server_create(gq_ctx *ctx, const gq_server_cfg *cfg, gq_server **out)
 {
-    if (!cfg || !out) return GQ_ERR_INVALID_ARG;
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if (!cfg || !out) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_server_create: NULL argument");
     *out = nullptr;
     const gq_server_tables &t = cfg->tables;
     if (t.n < 0 || t.n > GQ_MAX_ROWS || (t.n > 0 && (!t.fk || !t.fk2 || !t.date || !t.qty || !t.price || !t.disc)) ||
         !t.dim1_table || !t.dim2_table || !cfg->pool || cfg->pool_bytes < 4096 ||
         reinterpret_cast<uintptr_t>(cfg->pool) % 256 != 0 || cfg->streams < 1 || cfg->streams > 8 ||
         cfg->max_batch < 1 || cfg->max_batch > SV_MAX_BATCH)
-        return GQ_ERR_INVALID_ARG;
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_server_create: bad tables, pool or limits");
     gq_server *s = new gq_server();
-    s->device = device;
-    if (gq_ctx_create(device, &s->ctx) != GQ_OK) {
-        delete s;
-        return GQ_ERR_HIP;
-    }
+    s->device = ctx->device;
     auto log2_of = [](size_t bytes) {
         int L = 6;
         while (L < 40 && 256 + (size_t(2) << L) * 16 <= bytes) ++L;
@@ -245,14 +290,26 @@ gq_status gq_server_create(int device, const gq_server_cfg *cfg, gq_server **out
     s->alloc.init(cfg->pool_bytes);
     s->serial = cfg->serial != 0;
     s->max_batch = s->serial ? 1 : cfg->max_batch;
-    (void)hipSetDevice(device);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
     s->slots.resize(s->serial ? 1 : cfg->streams);
+    gq_status rc = GQ_OK;
     for (auto &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        if (gq_ctx_create(s->device, &sl.ctx) != GQ_OK ||
+            hipHostMalloc(reinterpret_cast<void **>(&sl.status_host), sizeof(uint32_t), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
-            gq_server_destroy(s);
-            return GQ_ERR_HIP;
+            rc = GQ_ERR_HIP;
+            break;
         }
+        *sl.status_host = 0;
+    }
+    (void)hipSetDevice(prev);
+    if (rc != GQ_OK) {
+        gq_server_destroy(s);
+        return gq_fail(ctx, rc, "gq_server_create: stream, event or context creation failed");
     }
     s->th = std::thread([s] { s->loop(); });
     *out = s;
@@ -313,13 +370,15 @@ gq_status gq_server_wait(gq_server *srv, uint64_t ticket, gq_status *query_statu
     return GQ_OK;
 }
 
-gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen)
+gq_status gq_server_stats(gq_server *srv, int64_t *done, int64_t *batches, int64_t *max_batch_seen,
+                          int64_t *reruns)
 {
     if (!srv) return GQ_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(srv->mu);
     if (done) *done = srv->n_done;
     if (batches) *batches = srv->n_batches;
     if (max_batch_seen) *max_batch_seen = srv->max_seen;
+    if (reruns) *reruns = srv->n_reruns;
     return GQ_OK;
 }
 
@@ -340,8 +399,9 @@ void gq_server_destroy(gq_server *srv)
             (void)hipStreamDestroy(sl.stream);
         }
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.status_host) (void)hipHostFree(sl.status_host);
+        if (sl.ctx) gq_ctx_destroy(sl.ctx);
     }
-    if (srv->ctx) gq_ctx_destroy(srv->ctx);
     delete srv;
 }
 

@@ -12,8 +12,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import (GQ_OK, GQ_QUERY_FILTER_AGG, GQ_QUERY_FILTER_TOPK, GQError, Query, ServerCfg, ServerTables,
-               _groups_struct, _ptr, alloc_groups, lib)
+from . import (GQ_ERR_CAPACITY, GQ_OK, GQ_QUERY_FILTER_AGG, GQ_QUERY_FILTER_TOPK, Context, GQError, Query,
+               ServerCfg, ServerTables, _groups_struct, _ptr, alloc_groups, lib)
 
 
 @dataclass
@@ -36,9 +36,14 @@ class Submitted:
 
 
 class Server:
-    def __init__(self, device: int, tables: dict, dim1_table: torch.Tensor, dim2_table: torch.Tensor,
+    """ctx: a Context, or a device index (a Context is then created for it)."""
+
+    def __init__(self, ctx, tables: dict, dim1_table: torch.Tensor, dim2_table: torch.Tensor,
                  pool: torch.Tensor, streams: int = 4, max_batch: int = 16, serial: bool = False):
-        self.device = torch.device("cuda", device)
+        if not isinstance(ctx, Context):
+            ctx = Context(int(ctx))
+        self.ctx = ctx
+        self.device = ctx.device
         self._keep = (tables, dim1_table, dim2_table, pool)
         t = ServerTables(_ptr(tables["fk"]), _ptr(tables["fk2"]), _ptr(tables["date"]), _ptr(tables["qty"]),
                          _ptr(tables["price"]), _ptr(tables["disc"]), tables["fk"].numel(), _ptr(dim1_table),
@@ -46,9 +51,7 @@ class Server:
         cfg = ServerCfg(t, _ptr(pool), pool.numel(), streams, max_batch, int(serial))
         h = C.c_void_p()
         torch.cuda.synchronize(self.device)
-        rc = lib().gq_server_create(device, C.byref(cfg), C.byref(h))
-        if rc != GQ_OK:
-            raise GQError(rc, "gq_server_create")
+        ctx.check(lib().gq_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
         self.h = h
 
     def alloc_output(self, spec: QuerySpec):
@@ -79,10 +82,26 @@ class Server:
         sub.status, sub.latency = st.value, lat.value
         return sub
 
+    def run(self, spec: QuerySpec, capacity: int | None = None, max_tries: int = 4) -> Submitted:
+        """Submit and wait, with the caller's recovery from GQ_ERR_CAPACITY: the
+        server already retries up to the output capacity, so a query that still
+        reports it is submitted again with outputs (and group bound) twice as
+        large, up to max_tries times."""
+        cap = capacity or spec.max_groups
+        for _ in range(max_tries):
+            sp = QuerySpec(spec.kind, spec.date_hi, max_groups=min(spec.max_groups, cap), k=spec.k)
+            out = self.alloc_output(QuerySpec(spec.kind, spec.date_hi, max_groups=cap, k=spec.k))
+            sub = self.wait(self.submit(sp, out=out))
+            if sub.status != GQ_ERR_CAPACITY or spec.kind == GQ_QUERY_FILTER_TOPK:
+                sub.extra["capacity"] = cap
+                return sub
+            cap *= 2
+        return sub
+
     def stats(self):
-        d, b, m = C.c_int64(), C.c_int64(), C.c_int64()
-        lib().gq_server_stats(self.h, C.byref(d), C.byref(b), C.byref(m))
-        return {"done": d.value, "batches": b.value, "max_batch": m.value}
+        d, b, m, r = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        lib().gq_server_stats(self.h, C.byref(d), C.byref(b), C.byref(m), C.byref(r))
+        return {"done": d.value, "batches": b.value, "max_batch": m.value, "reruns": r.value}
 
     def close(self):
         if getattr(self, "h", None):

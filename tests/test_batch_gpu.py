@@ -156,6 +156,82 @@ def test_batch_duplicate_key_reported(ctx):
     assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
 
 
+@pytest.mark.parametrize("bad_big", [False, True])
+def test_batch_error_flagged_per_instance(ctx, bad_big):
+    """One instance with a duplicate build key (built in LDS, or by device
+    compare-and-swap when its table is large): its own status says so, every
+    other instance reports GQ_OK and equals the oracle."""
+    spec = synth.BatchSpec(count=12, build_lo=200, build_hi=60_000, seed=synth.SEED_BASE + 95)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    sizes = [m for _, m, _, _ in layout]
+    bad = int(np.argmax(sizes)) if bad_big else int(np.argmin(sizes))
+    mo, m, _, _ = layout[bad]
+    assert (m > 4096 // 2) == bad_big                   # an LDS-built table only when small
+    orig = cols["dim_key"][mo + m - 1].clone()
+    cols["dim_key"][mo + m - 1] = cols["dim_key"][mo]
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    st = b.statuses()
+    assert ctx.status() == gq.GQ_ERR_DUPLICATE_KEY
+    assert st[bad] == gq.GQ_ERR_DUPLICATE_KEY
+    assert all(x == gq.GQ_OK for i, x in enumerate(st) if i != bad)
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    for i, (lay, g) in enumerate(zip(layout, b.results())):
+        if i != bad:
+            _equal(_sorted(g), _oracle(cols_h, lay, spec))
+    # the same batch without the error: every status back to GQ_OK, all exact
+    cols["dim_key"][mo + m - 1] = orig
+    b.run()
+    assert ctx.status() == gq.GQ_OK and all(x == gq.GQ_OK for x in b.statuses())
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    _equal(_sorted(b.results()[bad]), _oracle(cols_h, layout[bad], spec))
+
+
+def test_batch_int64_min_foreign_keys_match_nothing(ctx):
+    """A foreign key equal to INT64_MIN (the empty-slot marker) must not
+    match an empty slot: those rows drop out of the join, as in the oracle."""
+    spec = synth.BatchSpec(count=6, build_lo=100, build_hi=50_000, seed=synth.SEED_BASE + 97)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    r = np.random.default_rng(97)
+    nt = cols["fk"].numel()
+    hit = torch.from_numpy(r.random(nt) < 0.1).cuda()
+    cols["fk"].masked_fill_(hit, -(1 << 63))
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    b.run()
+    assert ctx.status() == gq.GQ_OK and all(x == gq.GQ_OK for x in b.statuses())
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    for lay, g in zip(layout, b.results()):
+        _equal(_sorted(g), _oracle(cols_h, lay, spec))
+
+
+def test_batch_wait_bound_forced_from_host(ctx):
+    """The bounded wait of the batch kernel, forced from the host with a
+    one-poll bound: probe and build items that find their inputs unfinished
+    skip their work and report GQ_ERR_TIMEOUT, and the kernel still drains its
+    queue and returns.  Back at the default bound the same batch is exact."""
+    spec = synth.BatchSpec(count=24, build_lo=5_000, build_hi=200_000, seed=synth.SEED_BASE + 99)
+    cols, layout = synth.batch_tables(spec, device="cuda")
+    b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
+    t = gq.gq_default_tuning()
+    t.lag = 0                                  # probes queued right behind their own builds
+    b.tuning = t
+    ctx.set_wait_limit(1)
+    try:
+        b.run()
+        torch.cuda.synchronize()
+        st = b.statuses()
+        word = ctx.status()
+    finally:
+        ctx.set_wait_limit(0)
+    assert word == gq.GQ_ERR_TIMEOUT
+    assert all(x in (gq.GQ_OK, gq.GQ_ERR_TIMEOUT) for x in st) and gq.GQ_ERR_TIMEOUT in st
+    b.run()
+    assert ctx.status() == gq.GQ_OK and all(x == gq.GQ_OK for x in b.statuses())
+    cols_h = {k: v.cpu().numpy() for k, v in cols.items()}
+    for lay, g in zip(layout, b.results()):
+        _equal(_sorted(g), _oracle(cols_h, lay, spec))
+
+
 def test_batch_full_size_sampled(ctx, tmp_path):
     """The benchmark's batched workload at full size (512 instances, build
     sizes log-uniform in [1e3, 2e6], probe sizes 8-16x build: 1.75G probe

@@ -29,3 +29,14 @@ def test_algorithmic_bytes_per_operator():
     assert by["topk"] == 12 * s_n + 12 * k
     assert bench.algorithmic_bytes(n, m, s_n, g, k, partition=False)["partition"] == 0
     assert sum(by.values()) == 26_609_162_936             # the bytes of one step of the 200M-row share
+
+
+def test_cpu_baseline_uses_several_cores():
+    """The CPU baseline runs the oracle's pipeline on one shard per thread and
+    reports the thread count, the CPU model and the one-core figure."""
+    import synth
+    w = synth.workload(0, scale=1 / 64)
+    r = bench.cpu_baseline(w, 4096, 2)
+    assert r["cores"] == 2 and r["kind"] == "oracle" and r["value"] > 0
+    assert r["single_core"]["cores"] == 1 and r["single_core"]["value"] > 0
+    assert r["cpu_model"]

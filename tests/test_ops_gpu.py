@@ -400,6 +400,26 @@ def test_groupby_no_key_and_empty(ctx):
     assert int(res.n_groups.item()) == 0
 
 
+@pytest.mark.parametrize("composite", [False, True])
+@pytest.mark.parametrize("max_groups", [1024, 4000])
+@pytest.mark.parametrize("n", [1, 2048, 5000, 16383])
+def test_groupby_large_path_few_rows(ctx, n, max_groups, composite):
+    """The large path (max_groups above the small path's bound) on inputs of
+    fewer than eight scatter tiles: the tiles are split over the eight XCD
+    ranges, some of them empty."""
+    rowid, key32, key64, qty, price, disc = _gb_inputs(n, n + 3, 31 + n, min(max_groups, 900))
+    if composite:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key64_by_rowid=True, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                                key64_by_rowid=True, key32=dev(key32), max_groups=max_groups)
+    else:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                                max_groups=max_groups)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, composite, True)
+
+
 def test_groupby_capacity_error(ctx):
     n = 5000
     key32 = np.arange(n, dtype=np.int32)

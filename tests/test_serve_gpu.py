@@ -227,3 +227,66 @@ def test_served_full_size_each_template():
     ev, er = oracle.topk(fact["price"][torch.from_numpy(cand).cuda()].cpu().numpy(), 100)
     assert np.array_equal(got[3]["row"], cand[er]) and np.array_equal(got[3]["val"], ev)
     ctx.close()
+
+
+def test_served_capacity_error_isolated_and_retried(served):
+    """Group overflow in the served path.  Outputs too small for a join +
+    aggregate query: the query reports GQ_ERR_CAPACITY, alone and inside a
+    burst of queries of its template, whose other queries report GQ_OK with
+    exact results.  A group bound below the true count but outputs large
+    enough: the server re-runs the query with a doubled bound and it is exact.
+    The caller's pattern (Server.run) doubles the outputs until it fits."""
+    spec, fact, t1, t2, pool, h = served
+    hi = 1200
+    full = QuerySpec(gq.GQ_QUERY_JOIN_AGG, hi, max_groups=spec.code_range)
+    exp = _norm(full, _oracle(full, h))
+    G = len(exp["count"])
+    assert G > 2000
+    srv = Server(0, fact, t1, t2, pool, streams=2, max_batch=16)
+    small = QuerySpec(gq.GQ_QUERY_JOIN_AGG, hi, max_groups=G // 4)       # outputs of G/4 groups
+    assert srv.wait(srv.submit(small)).status == gq.GQ_ERR_CAPACITY
+    good = [QuerySpec(gq.GQ_QUERY_JOIN_AGG, x, max_groups=spec.code_range) for x in (700, 2000)]
+    subs = [srv.submit(q) for q in (good[0], small, good[1], good[0])]
+    for s_ in subs:
+        srv.wait(s_)
+    assert [s_.status for s_ in subs] == [gq.GQ_OK, gq.GQ_ERR_CAPACITY, gq.GQ_OK, gq.GQ_OK]
+    for s_ in (subs[0], subs[2], subs[3]):
+        _same(s_.spec, _norm(s_.spec, result_host(s_)), _norm(s_.spec, _oracle(s_.spec, h)))
+    before = srv.stats()["reruns"]
+    out = srv.alloc_output(full)                                            # room for every group
+    sub = srv.wait(srv.submit(QuerySpec(gq.GQ_QUERY_JOIN_AGG, hi, max_groups=G // 8), out=out))
+    assert sub.status == gq.GQ_OK and srv.stats()["reruns"] > before
+    _same(full, _norm(full, result_host(sub)), exp)
+    sub = srv.run(small)
+    assert sub.status == gq.GQ_OK and sub.extra["capacity"] >= G
+    _same(full, _norm(full, result_host(sub)), exp)
+    srv.close()
+
+
+def test_served_int64_min_foreign_keys_match_nothing(served):
+    """Foreign keys equal to INT64_MIN (the empty-slot marker) drop out of
+    the join in the shared scans and the plain form alike, as in the oracle."""
+    spec, fact, t1, t2, pool, h = served
+    saved = {k: fact[k].clone() for k in ("fk", "fk2")}
+    hit = torch.from_numpy(np.random.default_rng(3).random(fact["fk"].numel()) < 0.05).cuda()
+    try:
+        fact["fk"].masked_fill_(hit, -(1 << 63))
+        fact["fk2"].masked_fill_(hit.roll(7), -(1 << 63))
+        hh = dict(h)
+        hh["fact"] = dict(h["fact"], fk=fact["fk"].cpu().numpy(), fk2=fact["fk2"].cpu().numpy())
+        qs = [QuerySpec(gq.GQ_QUERY_JOIN2_AGG, x, max_groups=32) for x in (500, 900, 1400, 2000)]
+        qs += [QuerySpec(gq.GQ_QUERY_JOIN_AGG, x, max_groups=spec.code_range) for x in (800, 1600)]
+        srv = Server(0, fact, t1, t2, pool, streams=2, max_batch=16)
+        res = _run(srv, qs, burst=True)
+        st = srv.stats()
+        srv.close()
+        ser = Server(0, fact, t1, t2, pool, serial=True)
+        res_s = _run(ser, qs, burst=True)
+        ser.close()
+        for q, a, b in zip(qs, res, res_s):
+            e = _norm(q, _oracle(q, hh))
+            _same(q, a, e)
+            _same(q, b, e)
+    finally:
+        for k, v in saved.items():
+            fact[k].copy_(v)
