@@ -133,6 +133,24 @@ gq_status gq_filter(gq_ctx *ctx, const void *col, int dtype, int64_t n, const in
                     int32_t *sel_out, int64_t *n_out_dev,
                     void *ws, size_t ws_bytes, gq_stream stream);
 
+/* The same filter with no workspace argument and no allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Its scratch (a dequeue
+ * counter and one look-back word per 32,768 rows, at most 512.25 KiB) is a
+ * static device array of the library, one per GPU, held until the process
+ * ends and located at context creation.  The call clears it with a kernel
+ * (no memset node) and calls no allocating routine.  Every call on one GPU
+ * shares that array: calls that may overlap on one GPU (other streams,
+ * other threads, other contexts) race and give undefined results; serialize
+ * them or use gq_filter with separate workspaces.
+ * Arguments and output as gq_filter.  Errors: as gq_filter, plus
+ * GQ_ERR_CAPACITY if n needs more scratch than the array holds (never for
+ * n <= 2^31 - 1, the row limit) and GQ_ERR_HIP if the array could not be
+ * located on this device. */
+gq_status gq_filter_noalloc(gq_ctx *ctx, const void *col, int dtype, int64_t n, const int64_t *n_dev,
+                            const int32_t *sel_in, int64_t lo, int64_t hi,
+                            int32_t *sel_out, int64_t *n_out_dev, gq_stream stream);
+
 /* ------------------------------------------------------------------------
  * Radix hash partition (the local half of a shuffle)
  * Paper: Sec. 2.2 (every process applies the same partitioning function to

@@ -36,7 +36,8 @@ GQ_I32, GQ_I64 = 4, 8
 EXPORTED = [
     "gq_ctx_create", "gq_ctx_destroy", "gq_last_error", "gq_status_word", "gq_set_wait_limit", "gq_set_timing",
     "gq_kernel_time",
-    "gq_reset_timing", "gq_filter_workspace_bytes", "gq_filter", "gq_radix_partition_workspace_bytes",
+    "gq_reset_timing", "gq_filter_workspace_bytes", "gq_filter", "gq_filter_noalloc",
+    "gq_radix_partition_workspace_bytes",
     "gq_radix_partition", "gq_join_table_bytes", "gq_join_build_workspace_bytes", "gq_join_build", "gq_join_probe_workspace_bytes",
     "gq_join_probe_partitioned_workspace_bytes", "gq_join_probe_partitioned",
     "gq_join_probe", "gq_groupby_workspace_bytes", "gq_groupby_agg", "gq_topk_workspace_bytes", "gq_topk",
@@ -130,6 +131,8 @@ def lib():
         L.gq_filter_workspace_bytes.argtypes = [i64]
         L.gq_filter.restype = st
         L.gq_filter.argtypes = [vp, vp, i32, i64, vp, vp, i64, i64, vp, vp, vp, sz, vp]
+        L.gq_filter_noalloc.restype = st
+        L.gq_filter_noalloc.argtypes = [vp, vp, i32, i64, vp, vp, i64, i64, vp, vp, vp]
         L.gq_radix_partition_workspace_bytes.restype = sz
         L.gq_radix_partition_workspace_bytes.argtypes = [i64, i32]
         L.gq_radix_partition.restype = st
@@ -270,6 +273,18 @@ def gq_filter(ctx: Context, col, lo: int, hi: int, sel_in=None, n: int | None = 
     ws = ws if ws is not None else ctx.workspace(need)
     ctx.check(lib().gq_filter(ctx.handle, _ptr(col), dtype, n, _ptr(n_dev), _ptr(sel_in), lo, hi, _ptr(out),
                               _ptr(n_out), _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return out, n_out
+
+
+def gq_filter_noalloc(ctx: Context, col, lo: int, hi: int, out, n_out, sel_in=None, n: int | None = None,
+                      n_dev=None):
+    """gq_filter with the library's static scratch instead of a workspace: the
+    caller passes preallocated outputs, nothing is allocated."""
+    dtype = {torch.int32: GQ_I32, torch.int64: GQ_I64}[col.dtype]
+    if n is None:
+        n = sel_in.numel() if sel_in is not None else col.numel()
+    ctx.check(lib().gq_filter_noalloc(ctx.handle, _ptr(col), dtype, n, _ptr(n_dev), _ptr(sel_in), lo, hi, _ptr(out),
+                                      _ptr(n_out), _stream(ctx.device)))
     return out, n_out
 
 

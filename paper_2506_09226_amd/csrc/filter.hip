@@ -24,12 +24,14 @@ struct filter_ws {
     uint64_t *status;
 };
 
+// A dequeue counter, then one look-back status word per group of FT_GROUP tiles.
 filter_ws filter_layout(gq_carver &c, int64_t n)
 {
     filter_ws w;
     const int64_t tiles = (n + FT_TILE - 1) / FT_TILE;
+    const int64_t groups = (tiles + FT_GROUP - 1) / FT_GROUP;
     w.tile_ctr = c.take<uint32_t>(64);
-    w.status = c.take<uint64_t>(static_cast<size_t>(tiles > 0 ? tiles : 1));
+    w.status = c.take<uint64_t>(static_cast<size_t>(groups > 0 ? groups : 1));
     return w;
 }
 
@@ -131,7 +133,29 @@ gq_status launch_filter(gq_ctx *ctx, const void *col, const int32_t *sel_in, int
                      static_cast<const T *>(col), sel_in, n, n_dev, lo, hi, out, n_out, w.tile_ctr, w.status);
 }
 
+// Scratch of gq_filter_noalloc, one copy per GPU for the life of the
+// process: the dequeue counter (64 words) and one look-back status word per
+// group of FT_GROUP tiles, enough for the largest accepted input
+// (GQ_MAX_ROWS rows: 65,536 groups), 512.25 KiB in all.
+constexpr int64_t FT_SCRATCH_GROUPS =
+    ((GQ_MAX_ROWS + FT_TILE - 1) / FT_TILE + FT_GROUP - 1) / FT_GROUP;
+constexpr size_t FT_SCRATCH_WORDS = 32 + static_cast<size_t>(FT_SCRATCH_GROUPS);   // 8-byte words
+__device__ __align__(256) uint64_t scratch[FT_SCRATCH_WORDS];
+
 }  // namespace
+
+// Device address of this library's filter scratch on the context's device
+// (the device must be current).  Host code uses this address, never the
+// array's name, which on the host is only a stand-in.
+gq_status gq_filter_scratch_setup(gq_ctx *ctx)
+{
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return gq_fail(ctx, GQ_ERR_HIP, "filter scratch address: %s", hipGetErrorString(e));
+    ctx->filter_scratch = p;
+    return GQ_OK;
+}
 
 extern "C" {
 
@@ -159,6 +183,35 @@ gq_status gq_filter(gq_ctx *ctx, const void *col, int dtype, int64_t n, const in
     gq_carver c(ws);
     filter_ws w = filter_layout(c, n);
     GQ_TRY(gq_zero(ctx, ws, c.off / 4, s));     // tile counter + tile status words
+    if (dtype == GQ_I32)
+        return sel_in ? launch_filter<int32_t, true>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s)
+                      : launch_filter<int32_t, false>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s);
+    return sel_in ? launch_filter<int64_t, true>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s)
+                  : launch_filter<int64_t, false>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s);
+}
+
+gq_status gq_filter_noalloc(gq_ctx *ctx, const void *col, int dtype, int64_t n, const int64_t *n_dev,
+                            const int32_t *sel_in, int64_t lo, int64_t hi, int32_t *sel_out, int64_t *n_out_dev,
+                            gq_stream stream)
+{
+    if (!ctx) return GQ_ERR_INVALID_ARG;
+    if ((!col && n > 0) || !sel_out || !n_out_dev)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter_noalloc: NULL column, output or count");
+    if (n < 0 || n > GQ_MAX_ROWS)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter_noalloc: n=%lld outside [0, %lld]", (long long)n,
+                       (long long)GQ_MAX_ROWS);
+    if (dtype != GQ_I32 && dtype != GQ_I64)
+        return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_filter_noalloc: bad dtype %d", dtype);
+    if (!ctx->filter_scratch) return gq_fail(ctx, GQ_ERR_HIP, "gq_filter_noalloc: no scratch on this device");
+    gq_carver need(nullptr);
+    filter_layout(need, n);
+    if (need.bytes() > FT_SCRATCH_WORDS * sizeof(uint64_t))
+        return gq_fail(ctx, GQ_ERR_CAPACITY, "gq_filter_noalloc: %lld rows need %zu scratch bytes, more than %zu",
+                       (long long)n, need.bytes(), FT_SCRATCH_WORDS * sizeof(uint64_t));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gq_carver c(ctx->filter_scratch);
+    filter_ws w = filter_layout(c, n);
+    GQ_TRY(gq_zero(ctx, ctx->filter_scratch, c.off / 4, s));   // a kernel: no memset node under capture
     if (dtype == GQ_I32)
         return sel_in ? launch_filter<int32_t, true>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s)
                       : launch_filter<int32_t, false>(ctx, col, sel_in, n, n_dev, lo, hi, sel_out, n_out_dev, w, s);

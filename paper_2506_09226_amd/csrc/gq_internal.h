@@ -24,6 +24,7 @@ struct gq_ctx {
     size_t lds_per_cu = 160 * 1024;
     uint32_t *status_dev = nullptr;          // bit (1 << code) per device error
     int64_t wait_limit = int64_t(1) << 24;   // polls of a bounded device-side wait
+    void *filter_scratch = nullptr;          // device address of gq_filter_noalloc's scratch
     std::string last_error;
     bool timing = false;
     std::vector<gq_timing_rec> pending;      // recorded, not yet collected

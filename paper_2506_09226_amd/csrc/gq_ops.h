@@ -34,3 +34,7 @@ struct gq_tile_count {
 };
 gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uint32_t *start, void *ws,
                           hipStream_t s, const char *name, const gq_tile_count *live = nullptr);
+
+// Look up, on the current device (the context's), the device address of the
+// filter's static scratch array used by gq_filter_noalloc.
+gq_status gq_filter_scratch_setup(gq_ctx *ctx);

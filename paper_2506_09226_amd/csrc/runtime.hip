@@ -4,6 +4,7 @@
 
 #include "gq_device.h"
 #include "gq_internal.h"
+#include "gq_ops.h"
 
 gq_status gq_fail(gq_ctx *ctx, gq_status code, const char *fmt, ...)
 {
@@ -66,7 +67,7 @@ gq_status gq_ctx_create(int device, gq_ctx **out)
         ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
     }
     if (hipMalloc(&ctx->status_dev, 256) != hipSuccess ||
-        hipMemset(ctx->status_dev, 0, 256) != hipSuccess) {
+        hipMemset(ctx->status_dev, 0, 256) != hipSuccess || gq_filter_scratch_setup(ctx) != GQ_OK) {
         if (ctx->status_dev) (void)hipFree(ctx->status_dev);
         (void)hipSetDevice(prev);
         delete ctx;

@@ -407,7 +407,8 @@ def test_groupby_large_path_few_rows(ctx, n, max_groups, composite):
     """The large path (max_groups above the small path's bound) on inputs of
     fewer than eight scatter tiles: the tiles are split over the eight XCD
     ranges, some of them empty."""
-    rowid, key32, key64, qty, price, disc = _gb_inputs(n, n + 3, 31 + n, min(max_groups, 900))
+    # at most 900 distinct keys; composite keys pair 3 key64 values with 300 key32 values
+    rowid, key32, key64, qty, price, disc = _gb_inputs(n, n + 3, 31 + n, 300 if composite else 900)
     if composite:
         exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key64_by_rowid=True, key32=key32)
         res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
