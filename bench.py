@@ -103,16 +103,34 @@ def load_traffic(kernel: str, workload: str):
         return None
 
 
+def _sysfs_clocks() -> dict:
+    """The current DPM level of each clock domain from the driver's sysfs
+    files (read only), e.g. {"card0": {"sclk": "2400Mhz", ...}}."""
+    import glob
+    out = {}
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_*")):
+        card = path.split("/")[4]
+        dom = path.rsplit("pp_dpm_", 1)[1]
+        try:
+            cur = [ln.split(":", 1)[1].strip(" *\n") for ln in open(path) if ln.rstrip().endswith("*")]
+        except OSError:
+            continue
+        if cur:
+            out.setdefault(card, {})[dom] = cur[0]
+    return out
+
+
 def gpu_clocks() -> dict:
-    """Current GPU clocks, power and temperature as rocm-smi reports them
-    (read only; an empty dict if the tool is unavailable)."""
+    """Current GPU clocks, power and temperature as rocm-smi reports them,
+    plus the sysfs DPM levels (read only; an error note if unavailable)."""
     import subprocess
+    sysfs = _sysfs_clocks()
     try:
         r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showtemp", "--json"],
                            capture_output=True, text=True, timeout=30)
         data = json.loads(r.stdout)
     except Exception as e:                                    # noqa: BLE001 - a missing tool is not an error
-        return {"error": str(e)[:120]}
+        return {"error": str(e)[:120], "sysfs_dpm": sysfs}
     out = {}
     for card, kv in data.items():
         if not isinstance(kv, dict):
@@ -124,6 +142,8 @@ def gpu_clocks() -> dict:
                                      "temperature (sensor memory)")):
                 keep[k] = v
         out[card] = keep
+    if sysfs:
+        out["sysfs_dpm"] = sysfs
     return out
 
 
@@ -283,7 +303,7 @@ def main():
     if args.workload == 1 and not args.no_served:
         out["served"] = bench_serve(args, sub=True)
         _release()
-    out["gpu_clocks"] = {"start": clk0, "end": gpu_clocks()}
+    out["gpu_clocks"] = {"start": clk0, **out["gpu_clocks"], "end": gpu_clocks()}
     if not args.no_cpu_baseline:
         import synth
         w = synth.workload(args.workload)
@@ -353,6 +373,7 @@ def bench_plain(args) -> dict:
     ms_step = e0.elapsed_time(e1) / args.steps
     ctx.set_timing(False)
     ctx.raise_status()
+    clk_steps = gpu_clocks()                   # read right after the timed steps, still in their clock state
     print(f"# {args.steps} steps: {ms_step:.3f} ms/step (host wall {1e3 * wall / args.steps:.3f} ms/step)",
           file=sys.stderr, flush=True)
     by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100, partition=not args.no_partition)
@@ -407,6 +428,7 @@ def bench_plain(args) -> dict:
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
         "roofline": roofline,
         "cpu_baseline": None,
+        "gpu_clocks": {"after_plain_steps": clk_steps},
     }
     del pl, fact, dim
     ctx.close()

@@ -4,9 +4,11 @@ top-k, on the seeded synthetic workloads.
 
   * small workload (1,048,576 x 65,536, 25 groups) at full size: every stage
     equals the oracle element by element.
-  * one-GPU share (200M x 25M, ~1.5M groups, 64 buckets) at full size:
-    sampled outputs recomputed row by row (the generator is counter based)
-    and checked by the oracle, plus invariants that hold at any size.
+  * one-GPU share (200M x 25M, ~1.5M groups, 64 buckets) and the skewed
+    workload (100M Zipf rows, ~10.6M composite groups) at full size: every
+    payload and every group against exact sums recomputed from the
+    generator (it is counter based), sampled rows by the oracle, plus
+    invariants that hold at any size.
   * skewed workload (Zipf foreign keys, composite group key) at 1/100 size:
     element by element.
 """
@@ -52,6 +54,32 @@ def _tables(w, device):
     fact = synth.fact_table(w.fact, device=device)
     dim = synth.dim_table(w.dim_m, w.dim_seed, w.attr_range, device=device)
     return fact, dim
+
+
+def _expected_groups_gpu(gid, qty, rev, nbins):
+    """Exact count, sum(qty) and sum(revenue) per group id in [0, nbins) by
+    integer scatter-adds on the GPU (every sum here fits int64: revenues are
+    below 2^31 and there are fewer than 2^32 rows)."""
+    cnt = torch.bincount(gid, minlength=nbins)
+    sq = torch.zeros(nbins, dtype=torch.int64, device=gid.device).scatter_add_(0, gid, qty)
+    sr = torch.zeros(nbins, dtype=torch.int64, device=gid.device).scatter_add_(0, gid, rev)
+    return cnt, sq, sr
+
+
+def _check_every_group(res_count, res_sq, res_lo, res_hi, res_aq, res_ar, ids, cnt, sq, sr):
+    """The result's groups, mapped to their ids, against the expected arrays:
+    every group with rows is present once, and every field is exact (the
+    float64 averages from the exact integers, within the stated tolerance)."""
+    ng = res_count.numel()
+    assert ng == int((cnt > 0).sum().item())
+    assert int(torch.unique(ids).numel()) == ng
+    assert torch.equal(res_count, cnt[ids]) and torch.equal(res_sq, sq[ids])
+    assert bool((res_hi == 0).all()) and torch.equal(res_lo, sr[ids])
+    c = cnt[ids].to(torch.float64)
+    aq = (sq[ids].to(torch.float64) / c).cpu().numpy()
+    ar = (sr[ids].to(torch.float64) / c).cpu().numpy()
+    np.testing.assert_allclose(res_aq.cpu().numpy(), aq, rtol=AVG_RTOL, atol=0)
+    np.testing.assert_allclose(res_ar.cpu().numpy(), ar, rtol=AVG_RTOL, atol=0)
 
 
 @pytest.mark.parametrize("probe,streams", [("ordered", 2), ("partitioned", 2), ("partitioned", 1), ("tune", 1)])
@@ -153,11 +181,14 @@ def test_skewed_workload_reduced(ctx):
     assert np.array_equal(H(pl.tk_val), ev) and np.array_equal(H(pl.tk_row), er)
 
 
-def test_skewed_workload_full_size_sampled(ctx):
+def test_skewed_workload_full_size(ctx):
     """100M fact rows with Zipf(1.0) foreign keys over a 10M-row dimension:
     the composite-key group-by over all rows (about ten million groups) and
-    the 5% filter -> join -> group-by pipeline, checked by totals, the exact
-    distinct count and sampled groups recomputed by the oracle."""
+    the 5% filter -> join -> group-by -> top-100 pipeline.  Every composite
+    group, every payload and every group of the pipeline exactly against sums
+    recomputed from the generator; the totals, the exact distinct count, the
+    heaviest group and three sampled ones also by the oracle; the top-100 by
+    the oracle over its candidate rows."""
     w = synth.workload(2)
     fact, dim = _tables(w, "cuda")
     n = w.fact.n
@@ -166,6 +197,35 @@ def test_skewed_workload_full_size_sampled(ctx):
     torch.cuda.synchronize()
     assert ctx.status() == gq.GQ_OK
     ng = int(res.n_groups.item())
+
+    # every composite group: expected sums per (dim row, g32) id from the
+    # generator's Zipf draw; result groups are mapped to ids by sorting both
+    # sides on (key64, key32)
+    rows_all = torch.arange(n, dtype=torch.int64, device="cuda")
+    frow = synth.zipf_row(w.fact.seed, synth.S_FK_ROW, rows_all, w.dim_m, 1.0)
+    gid = frow * 2 + fact["g32"].long()
+    del rows_all, frow
+    ecnt, esq, esr = _expected_groups_gpu(gid, fact["qty"], fact["price"] * (100 - fact["disc"]), 2 * w.dim_m)
+    del gid
+    eids = torch.nonzero(ecnt > 0).flatten()
+    assert eids.numel() == ng
+    ek64 = synth.dim_key(w.dim_seed, eids // 2)
+    ek32 = (eids % 2).to(torch.int32)
+
+    def lex(k64, k32):
+        o = torch.sort(k32, stable=True)[1]
+        return o[torch.sort(k64[o], stable=True)[1]]
+
+    oe = lex(ek64, ek32)
+    orr = lex(res.key64[:ng], res.key32[:ng])
+    assert torch.equal(res.key64[:ng][orr], ek64[oe]) and torch.equal(res.key32[:ng][orr], ek32[oe])
+    ids = eids[oe]                                    # the id of each result group, in result order orr
+    inv = torch.empty_like(orr)
+    inv[orr] = torch.arange(ng, device="cuda")
+    ids_in_result_order = ids[inv]
+    _check_every_group(res.count[:ng], res.sum_qty[:ng], res.sum_rev_lo[:ng], res.sum_rev_hi[:ng],
+                       res.avg_qty[:ng], res.avg_rev[:ng], ids_in_result_order, ecnt, esq, esr)
+    del ecnt, esq, esr, eids, ek64, ek32, oe, orr, ids, inv, ids_in_result_order
     fk, g32 = fact["fk"], fact["g32"]
     distinct = sum(int(torch.unique(fk[g32 == g]).numel()) for g in (0, 1))
     assert ng == distinct and 8_000_000 < ng < 12_000_000
@@ -191,15 +251,38 @@ def test_skewed_workload_full_size_sampled(ctx):
     assert ctx.status() == gq.GQ_OK
     ns, nj = int(pl.n_sel.item()), int(pl.n_join.item())
     assert ns == int((fact["date"] < w.date_hi).sum().item()) and nj == ns
-    g = pl.groups.host()
-    assert int(g["count"].sum()) == nj
+    # every group of the 5% pipeline (group by the dimension attribute of the
+    # joined row) against exact sums over the selected rows
+    keep = torch.nonzero(fact["date"] < w.date_hi).flatten()
+    assert torch.equal(pl.sel[:ns].long(), keep)
+    frow = synth.zipf_row(w.fact.seed, synth.S_FK_ROW, keep, w.dim_m, 1.0)
+    attr = synth.dim_columns(w.dim_seed, frow, w.attr_range)["attr"]
+    assert torch.equal(pl.pay[:nj], attr)
+    ecnt, esq, esr = _expected_groups_gpu(attr.long(), fact["qty"][keep],
+                                          fact["price"][keep] * (100 - fact["disc"][keep]), w.attr_range)
+    gg = pl.groups
+    ng5 = int(gg.n_groups.item())
+    _check_every_group(gg.count[:ng5], gg.sum_qty[:ng5], gg.sum_rev_lo[:ng5], gg.sum_rev_hi[:ng5],
+                       gg.avg_qty[:ng5], gg.avg_rev[:ng5], gg.key32[:ng5].long(), ecnt, esq, esr)
+    # the top-100 of price over the selection: the oracle over every selected
+    # row whose price reaches the 100th value
+    v, r = H(pl.tk_val), H(pl.tk_row)
+    t = int(v[-1])
+    psel = fact["price"][keep]
+    cand = keep[psel >= t].to(torch.int32)
+    assert int((psel > t).sum().item()) < 100 <= cand.numel()
+    ev, er = oracle.topk(H(fact["price"]), 100, sel=H(cand))
+    assert np.array_equal(v, ev) and np.array_equal(r, er)
 
 
 @pytest.mark.parametrize("probe", ["partitioned", "ordered"])
-def test_one_gpu_share_full_size_sampled(ctx, probe):
+def test_one_gpu_share_full_size(ctx, probe):
     """200M fact rows, 25M dim rows, 64 buckets, ~1.5M groups: the benchmark's
-    launch configuration (partitioned probe) and the ordered probe, checked on
-    sampled outputs and invariants."""
+    launch configuration (partitioned probe) and the ordered probe.  Every
+    probe payload and every group is checked exactly against values
+    recomputed from the generator; the partition on sampled rows plus
+    invariants (permutation, stability, bucket of each row); four groups and
+    the top-100 also by the oracle."""
     w = synth.workload(1)
     fact, dim = _tables(w, "cuda")
     n, m = w.fact.n, w.dim_m
@@ -239,26 +322,29 @@ def test_one_gpu_share_full_size_sampled(ctx, probe):
     sel = pl.sel[:ns]
     assert bool((sel[1:] > sel[:-1]).all()) and bool((pdate[sel.long()] < w.date_hi).all())
 
-    # join: every foreign key references a dim key -> |join| = |sel|, rows = selection
+    # join: every foreign key references a dim key -> |join| = |sel|, rows = selection;
+    # every payload against the dimension attribute of its row's foreign key,
+    # recomputed from the generator's counter-based draw (no operator involved)
     nj = int(pl.n_join.item())
     assert nj == ns and torch.equal(pl.prow[:nj], sel)
-    i = np.sort(rs.integers(0, nj, size=20_000))
-    it = torch.from_numpy(i).cuda()
-    src = H(rowid[pl.prow[it].long()]).astype(np.int64)
-    u = synth.uniform_int(w.fact.seed, synth.S_FK_ROW, torch.from_numpy(src), 0, m - 1)
-    attr = synth.dim_columns(w.dim_seed, u, w.attr_range)["attr"].numpy()
-    assert np.array_equal(H(pl.pay[it]), attr)
-
-    # group-by: totals and sampled groups recomputed by the oracle
-    g = pl.groups.host()
-    ng = len(g["count"])
-    assert 0.99 * w.attr_range < ng <= w.attr_range
-    assert int(g["count"].sum()) == nj
     prow = pl.prow[:nj].long()
+    src_all = rowid[prow].long()
+    u_all = synth.uniform_int(w.fact.seed, synth.S_FK_ROW, src_all, 0, m - 1)
+    attr_all = synth.dim_columns(w.dim_seed, u_all, w.attr_range)["attr"]
+    assert torch.equal(pl.pay[:nj], attr_all)
+    del u_all, src_all
+
+    # group-by: every group against exact integer sums over its rows
     _, pqty, pprice, pdisc = pl.p_cols
-    assert int(g["sum_qty"].sum()) == int(pqty[prow].sum().item())
-    rev_total = int((pprice[prow] * (100 - pdisc[prow])).sum().item())
-    assert np.all(g["sum_rev_hi"] == 0) and sum(int(x) for x in g["sum_rev_lo"]) == rev_total
+    gq_ = pl.groups
+    ng = int(gq_.n_groups.item())
+    assert 0.99 * w.attr_range < ng <= w.attr_range
+    ecnt, esq, esr = _expected_groups_gpu(attr_all.long(), pqty[prow], pprice[prow] * (100 - pdisc[prow]),
+                                          w.attr_range)
+    _check_every_group(gq_.count[:ng], gq_.sum_qty[:ng], gq_.sum_rev_lo[:ng], gq_.sum_rev_hi[:ng],
+                       gq_.avg_qty[:ng], gq_.avg_rev[:ng], gq_.key32[:ng].long(), ecnt, esq, esr)
+    del ecnt, esq, esr, attr_all
+    g = pl.groups.host()
     pick = rs.choice(ng, size=4, replace=False)
     pay = pl.pay[:nj]
     for gi in pick:
