@@ -166,51 +166,89 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     int probes = 0, found = -1;
     bool done = !active;
     if constexpr (!K64) {
+        // Linear probing over groups of four slots: the four words of a group
+        // are read together (four independent 64-bit loads), the key is
+        // looked for in all of them, and a missing key claims the group's
+        // first empty slot with one compare-and-swap (re-reading the group if
+        // another lane took that slot first).  A key therefore sits in the
+        // first group from its home group that had room when it arrived, and
+        // slots never empty again, so a lookup may stop at the first group
+        // with an empty slot.  The wave-uniform loop runs as long as the
+        // longest chain of the wave, in groups instead of slots.
         const unsigned long long want = (static_cast<unsigned long long>(static_cast<uint32_t>(k32)) << 32) | 1ull;
+        uint32_t g = s >> 2;
         while (__any(!done)) {
             if (!done) {
-                unsigned long long *wp = reinterpret_cast<unsigned long long *>(&T.word[s]);
-                unsigned long long w = __hip_atomic_load(wp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (w == 0ull) {
-                    w = atomicCAS(wp, 0ull, want);
-                    if (w == 0ull) w = want;                  // claimed
+                unsigned long long *gp = reinterpret_cast<unsigned long long *>(&T.word[4 * g]);
+                unsigned long long w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = __hip_atomic_load(gp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                int hit = -1, empty = -1;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    if (w[i] == want) hit = i;
+                    if (w[i] == 0ull) empty = i;
                 }
-                if (w == want) {
-                    found = static_cast<int>(s);
+                if (hit >= 0) {
+                    found = static_cast<int>(4 * g) + hit;
                     done = true;
-                } else if (++probes >= GB_LDS_PROBES) {
+                } else if (empty >= 0) {
+                    const unsigned long long prev = atomicCAS(gp + empty, 0ull, want);
+                    if (prev == 0ull || prev == want) {      // claimed, or the key arrived there meanwhile
+                        found = static_cast<int>(4 * g) + empty;
+                        done = true;
+                    }                                         // else: the slot went to another key; read again
+                } else if (++probes >= GB_LDS_PROBES / 4) {
                     done = true;
                 } else {
-                    s = (s + 1 == SLOTS) ? 0 : s + 1;
+                    g = (g + 1 == SLOTS / 4) ? 0 : g + 1;
                 }
             }
         }
     } else {
-    while (__any(!done)) {
-        if (!done) {
-            // read first: most visits find a published key and need no atomic
-            uint32_t st = __hip_atomic_load(&T.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (st == 0u) st = atomicCAS(&T.state[s], 0u, 1u);
-            if (st == 0u) {
-                T.k64[s] = k64;
-                if (K32) T.k32[s] = k32;
-                __threadfence_block();
-                atomicExch(&T.state[s], 2u);
-                found = static_cast<int>(s);
-                done = true;
-            } else if (st == 2u) {
-                const bool eq = T.k64[s] == k64 && (!K32 || T.k32[s] == k32);
-                if (eq) {
-                    found = static_cast<int>(s);
+        // The same groups of four slots for tables keyed by key64: the four
+        // state words are read first; the keys of the published slots are
+        // compared; a slot being claimed (state 1) may be getting this very
+        // key, so the group is read again until it is published; with no
+        // match and no claim in progress the first empty slot is claimed.
+        uint32_t g = s >> 2;
+        while (__any(!done)) {
+            if (!done) {
+                uint32_t st[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    st[i] = __hip_atomic_load(&T.state[4 * g + i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                int hit = -1, empty = -1;
+                bool claiming = false;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    const int sl = static_cast<int>(4 * g) + i;
+                    if (st[i] == 2u && T.k64[sl] == k64 && (!K32 || T.k32[sl] == k32)) hit = i;
+                    if (st[i] == 0u) empty = i;
+                    claiming = claiming || st[i] == 1u;
+                }
+                if (hit >= 0) {
+                    found = static_cast<int>(4 * g) + hit;
                     done = true;
-                } else if (++probes >= GB_LDS_PROBES) {
+                } else if (claiming) {
+                    // read the group again on the next pass
+                } else if (empty >= 0) {
+                    const int sl = static_cast<int>(4 * g) + empty;
+                    if (atomicCAS(&T.state[sl], 0u, 1u) == 0u) {
+                        T.k64[sl] = k64;
+                        if (K32) T.k32[sl] = k32;
+                        __threadfence_block();
+                        atomicExch(&T.state[sl], 2u);
+                        found = sl;
+                        done = true;
+                    }                                         // else: taken meanwhile; read again
+                } else if (++probes >= GB_LDS_PROBES / 4) {
                     done = true;
                 } else {
-                    s = (s + 1 == SLOTS) ? 0 : s + 1;
+                    g = (g + 1 == SLOTS / 4) ? 0 : g + 1;
                 }
             }
         }
-    }
     }
     return found;
 }

@@ -47,12 +47,15 @@ struct tk_lds {
 };
 
 // Bitonic sort, best first, of the first `size` (power of two) entries.
+// Stage (k, j) compares entries lo and lo + j, where lo is the i-th index
+// with bit j clear: i with a zero inserted at bit position log2(j) (shifts
+// and masks, no integer division).
 GQ_DEV void tk_sort(tk_lds &L, int size)
 {
     for (int k = 2; k <= size; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < size / 2; i += TK_THREADS) {
-                const int lo = 2 * j * (i / j) + (i % j);
+                const int lo = ((i & ~(j - 1)) << 1) | (i & (j - 1));
                 const int hi = lo + j;
                 const bool best_first = (lo & k) == 0;
                 const uint64_t aok = L.ok[lo], bok = L.ok[hi];
@@ -224,7 +227,8 @@ __global__ __launch_bounds__(TK_THREADS) void topk_merge_kernel(const uint64_t *
             valid[c] = false;
             ok[c] = 0;
             rk[c] = 0;
-            if (j < total && static_cast<uint32_t>(j % k) < in_cnt[b0 + j / k]) {
+            const uint32_t li = static_cast<uint32_t>(j) / static_cast<uint32_t>(k);    // total < 2^31
+            if (j < total && static_cast<uint32_t>(j) - li * static_cast<uint32_t>(k) < in_cnt[b0 + li]) {
                 valid[c] = true;
                 ok[c] = in_ok[base + j];
                 rk[c] = in_rk[base + j];
