@@ -66,8 +66,8 @@ OP_KERNELS = {
                    "gq_join_build_bounds", "gq_join_build_regions", "gq_join_build_overflow"],
     "join_probe": ["gq_join_probe", "gq_join_probe_split", "gq_join_probe_plan", "gq_join_probe_regions",
                    "gq_join_probe_compact"],
-    "groupby": ["gq_groupby_hist", "gq_groupby_scan", "gq_groupby_scatter", "gq_groupby_side", "gq_groupby_chunks",
-                "gq_groupby_bucket",
+    "groupby": ["gq_groupby_hist", "gq_groupby_scan", "gq_groupby_scatter", "gq_groupby_tiles2", "gq_groupby_hist2",
+                "gq_groupby_scan2", "gq_groupby_scatter2", "gq_groupby_side", "gq_groupby_chunks", "gq_groupby_bucket",
                 "gq_groupby_emit", "gq_groupby_local"],
     "topk": ["gq_topk_local", "gq_topk_merge"],
 }
@@ -590,6 +590,8 @@ def bench_batch(args, sub: bool = False) -> dict:
            "ms": round(ms_b, 4), "algorithmic_bytes": by, "GB/s": round(by / (ms_b * 1e6), 1),
            "frac_of_peak": round(by / (ms_b * 1e6) / HBM_PEAK_GBS, 4), "tuning": tun.as_dict(),
            "tuning_ms": round(tune_ms, 4),
+           "tuning_search": "coordinate descent, 2 rounds: load factor {0.2,0.25,0.3,0.4,0.5,0.6,0.7}, probe tile "
+                            "{8K..512K} rows, lag {1..64}, probe fan-out {1,2,4,8,16}, build tile {1K..64K}",
            "plain_per_instance": {"ms": round(ms_p, 3), "GB/s": round(by / (ms_p * 1e6), 1),
                                   "launch_chains": len(layout), "steps": max(1, args.steps // 2)},
            "speedup_vs_plain": round(ms_p / ms_b, 3), "results_equal": same}

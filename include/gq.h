@@ -379,10 +379,16 @@ typedef struct gq_tuning {
     int32_t init_tile;         /* slots per table-fill work item            */
     int32_t lag;               /* probe items of instance i follow the build
                                   items of instance i + lag in the queue    */
+    int32_t fanout;            /* probe fan-out, 1..64: the probe tiles of
+                                  `fanout` consecutive instances are
+                                  interleaved in the queue (1: one instance's
+                                  tiles after another's, so every workgroup
+                                  probes the same table; more: several tables
+                                  probed at once)                           */
 } gq_tuning;
 
 /* Defaults: load factor 0.5, 8192-row probe tiles, 4096-key build tiles,
- * 16384-slot fill tiles, lag 2. */
+ * 16384-slot fill tiles, lag 2, fan-out 1. */
 gq_tuning gq_default_tuning(void);
 
 /* Workspace for gq_batch_join_agg (0 for invalid arguments).  It holds every
@@ -407,11 +413,16 @@ size_t gq_batch_workspace_bytes(const gq_instance *inst, int n_inst, const gq_tu
 gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, const gq_tuning *tuning,
                             gq_status *inst_status_dev, void *ws, size_t ws_bytes, gq_stream stream);
 
-/* Autotuner: times every candidate tuning (load factor x probe tile x lag) on
- * the given instances and returns the fastest in *best (its time in
- * *best_ms).  cache_path (nullable) names a text file: a tuning already stored
- * for the same instance sizes is returned without timing; a new result is
- * appended.  Synchronizes the stream.  ws must hold
+/* Autotuner: searches the tunings by coordinate descent over five axes
+ * (load factor 0.2..0.7, probe tile 8K..512K rows, lag 1..64, probe fan-out
+ * 1..16, build tile 1K..64K keys): from a starting point each axis in turn is
+ * swept with the others fixed, each point timed on the stream (a warm-up run,
+ * then one timed run), and its best value kept, for up to two rounds.  The
+ * fastest tuning goes to *best (its time in *best_ms).  cache_path (nullable)
+ * names a text file: a tuning already stored for the same workload signature
+ * (device compute units and LDS; per instance m, n, date range and group
+ * capacity) is returned without timing; a new result is appended.
+ * Synchronizes the stream.  ws must hold
  * gq_batch_autotune_workspace_bytes(inst, n_inst). */
 size_t gq_batch_autotune_workspace_bytes(const gq_instance *inst, int n_inst);
 gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, const char *cache_path,

@@ -94,7 +94,7 @@ class Query(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("load_factor", C.c_double), ("probe_tile", C.c_int32), ("build_tile", C.c_int32),
-                ("init_tile", C.c_int32), ("lag", C.c_int32)]
+                ("init_tile", C.c_int32), ("lag", C.c_int32), ("fanout", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -173,17 +173,6 @@ GQ_DEV int lds_group(bt_lds &T, bool active, int32_t key)
     return found;
 }
 
-// one row into LDS slot s (revenue known to fit 64 bits)
-GQ_DEV void lds_add_row(bt_lds &T, int s, int64_t qty, int64_t rev)
-{
-    atomicAdd(&T.cnt[s], 1u);
-    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[s]), static_cast<unsigned long long>(qty));
-    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[s]),
-              static_cast<unsigned long long>(static_cast<uint32_t>(static_cast<uint64_t>(rev))));
-    const int64_t high = rev >> 32;
-    if (high) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[s]), static_cast<unsigned long long>(high));
-}
-
 GQ_DEV gq_i128 split_total(uint64_t lo_sum, int64_t hi_sum)
 {
     const __int128 v = static_cast<__int128>(hi_sum) * (static_cast<__int128>(1) << 32) + static_cast<__int128>(lo_sum);
@@ -425,7 +414,28 @@ __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds
             const gq_i128 rev = hit[c] ? gq_revenue(pr[c], I.rev_scale, ds[c]) : gq_i128{0, 0};
             const bool fits = rev.hi == (static_cast<int64_t>(rev.lo) >> 63);
             const int slot = lds_group(T, hit[c] && fits, g[c]);
-            if (hit[c] && fits && slot >= 0) lds_add_row(T, slot, q[c], static_cast<int64_t>(rev.lo));
+            // An instance has few groups, so many lanes of a wave add to the
+            // same slot: the lanes of one slot are summed across the wave and
+            // added by one lane, slot after slot.  Revenues are summed split:
+            // the low 32 bits (unsigned) into lo[], the high 32 bits (signed)
+            // into hi[] (a slot's low-half sum over 64 lanes stays below 2^38).
+            bool mine = hit[c] && fits && slot >= 0;
+            for (uint64_t am = gq_ballot(mine); am; am = gq_ballot(mine)) {
+                const int lead = __builtin_ctzll(am);
+                const int sl = __builtin_amdgcn_readlane(slot, lead);
+                const bool in = mine && slot == sl;
+                const uint32_t cn = static_cast<uint32_t>(__popcll(gq_ballot(in)));
+                const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
+                const uint64_t lo = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(static_cast<uint32_t>(rev.lo)) : 0ull);
+                const int64_t hs = gq_wave_sum<int64_t>(in ? (static_cast<int64_t>(rev.lo) >> 32) : 0);
+                if (gq_lane() == lead) {
+                    atomicAdd(&T.cnt[sl], cn);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[sl]), static_cast<unsigned long long>(sq));
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[sl]), static_cast<unsigned long long>(lo));
+                    if (hs) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[sl]), static_cast<unsigned long long>(hs));
+                }
+                mine = mine && !in;
+            }
             // a full LDS table or a revenue wider than 64 bits goes to the global table
             const bool spill = hit[c] && (!fits || slot < 0);
             const int64_t gs = global_group(I, spill, g[c], status);
@@ -580,6 +590,8 @@ uint64_t pow2_at_least(uint64_t x)
 struct bt_plan {
     std::vector<bt_inst> insts;
     std::vector<bt_seg> segs;
+    bt_inst *insts_dev = nullptr;  // where the workspace holds the descriptors
+    bt_seg *segs_dev = nullptr;    //   and the segment table
     int64_t total_items = 0;
     size_t bytes = 0;              // workspace bytes
     size_t zero_bytes = 0;         // prefix to clear (counters, group tables)
@@ -589,7 +601,8 @@ bool valid_tuning(const gq_tuning &t)
 {
     return t.load_factor > 0.0 && t.load_factor <= 0.9 && t.probe_tile >= 4096 && t.probe_tile % 4096 == 0 &&
            t.probe_tile <= (1 << 22) && t.build_tile >= BT_THREADS && t.build_tile % BT_THREADS == 0 &&
-           t.init_tile >= BT_THREADS && t.init_tile % BT_THREADS == 0 && t.lag >= 0 && t.lag <= 1024;
+           t.init_tile >= BT_THREADS && t.init_tile % BT_THREADS == 0 && t.lag >= 0 && t.lag <= 1024 &&
+           t.fanout >= 1 && t.fanout <= 64;
 }
 
 // Lay the workspace out: [work counter | per-instance counters | group tables]
@@ -617,9 +630,7 @@ bt_plan make_plan(const gq_instance *in, int n, const gq_tuning &t, char *base)
         I.counters = ctrs[i];
     }
     pl.zero_bytes = c.off;
-    c.take<bt_inst>(static_cast<size_t>(n));
-    // segments: at most 3 per instance (+1 guard)
-    c.take<bt_seg>(static_cast<size_t>(3 * n + 1));
+    pl.insts_dev = c.take<bt_inst>(static_cast<size_t>(n));
     for (int i = 0; i < n; ++i) {
         bt_inst &I = pl.insts[i];
         const gq_instance &s = in[i];
@@ -646,7 +657,6 @@ bt_plan make_plan(const gq_instance *in, int n, const gq_tuning &t, char *base)
         I.build_items = lds ? 1 : static_cast<int32_t>((s.m + t.build_tile - 1) / t.build_tile);
         I.probe_items = static_cast<int32_t>((s.n + t.probe_tile - 1) / t.probe_tile);
     }
-    pl.bytes = c.bytes();
     // queue order: setup (init + build) of instance i, then probes of instance i - lag
     auto push = [&](int kind, int i, int64_t cnt) {
         if (cnt <= 0) return;
@@ -667,11 +677,39 @@ bt_plan make_plan(const gq_instance *in, int n, const gq_tuning &t, char *base)
             push(K_BUILD, i, I.build_items);
         }
     };
+    // probe items: instances in groups of `fanout`; the probe tiles of a
+    // group's instances are interleaved one by one (fanout 1: instance after
+    // instance), so that many instances' probes are in flight together or
+    // one instance's table is probed by every workgroup at once
+    auto push_probes = [&](int g0, int g1) {
+        if (g1 - g0 == 1) {
+            push(K_PROBE, g0, pl.insts[g0].probe_items);
+            return;
+        }
+        int32_t most = 0;
+        for (int i = g0; i < g1; ++i) most = std::max(most, pl.insts[i].probe_items);
+        for (int32_t tile = 0; tile < most; ++tile)
+            for (int i = g0; i < g1; ++i)
+                if (tile < pl.insts[i].probe_items) {
+                    bt_seg sg;
+                    sg.first_item = pl.total_items;
+                    sg.kind = K_PROBE;
+                    sg.inst = i;
+                    sg.first_tile = tile;
+                    sg.ntiles = 1;
+                    pl.segs.push_back(sg);
+                    pl.total_items += 1;
+                }
+    };
+    const int F = std::max(1, t.fanout);
     for (int i = 0; i < n + t.lag; ++i) {
         if (i < n) push_setup(i);
         const int j = i - t.lag;
-        if (j >= 0 && j < n) push(K_PROBE, j, pl.insts[j].probe_items);
+        if (j >= 0 && j < n && (j % F == F - 1 || j == n - 1)) push_probes(j - j % F, j + 1);
     }
+    // the segment table goes last: its length depends on the fan-out
+    pl.segs_dev = c.take<bt_seg>(pl.segs.size() + 1);
+    pl.bytes = c.bytes();
     return pl;
 }
 
@@ -687,6 +725,7 @@ gq_tuning gq_default_tuning(void)
     t.build_tile = 4096;
     t.init_tile = 16384;
     t.lag = 2;
+    t.fanout = 1;
     return t;
 }
 
@@ -723,9 +762,8 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
     bt_plan pl = make_plan(inst, n_inst, t, base);
     gq_carver c(base);
     uint32_t *work = c.take<uint32_t>(64);
-    c.off = pl.zero_bytes;
-    bt_inst *d_insts = c.take<bt_inst>(static_cast<size_t>(n_inst));
-    bt_seg *d_segs = c.take<bt_seg>(static_cast<size_t>(3 * n_inst + 1));
+    bt_inst *d_insts = pl.insts_dev;
+    bt_seg *d_segs = pl.segs_dev;
     GQ_TRY(gq_zero(ctx, ws, pl.zero_bytes / 4, s));
     GQ_CHECK_HIP(ctx, hipMemcpyAsync(d_insts, pl.insts.data(), sizeof(bt_inst) * n_inst, hipMemcpyHostToDevice, s));
     if (!pl.segs.empty())
@@ -779,23 +817,47 @@ uint64_t batch_signature(const gq_ctx *ctx, const gq_instance *in, int n)
     return h;
 }
 
-std::vector<gq_tuning> candidates()
+// The search space, one axis per tuning field.  The search is coordinate
+// descent: from a starting point, each axis in turn is swept with the others
+// fixed and its best value kept, for two rounds; each axis reaches beyond the
+// values that win on the MI355X, so the winner lies inside the grid.
+constexpr double TUNE_LF[] = {0.2, 0.25, 0.3, 0.4, 0.5, 0.6, 0.7};
+constexpr int TUNE_TILE[] = {8192, 16384, 32768, 65536, 131072, 262144, 524288};
+constexpr int TUNE_LAG[] = {1, 2, 4, 8, 16, 32, 64};
+constexpr int TUNE_FANOUT[] = {1, 2, 4, 8, 16};
+constexpr int TUNE_BUILD[] = {1024, 4096, 16384, 65536};
+constexpr int TUNE_ROUNDS = 2;
+
+gq_tuning tune_start()
+{
+    gq_tuning t = gq_default_tuning();
+    t.probe_tile = 65536;
+    t.lag = 4;
+    return t;
+}
+
+bool same_tuning(const gq_tuning &a, const gq_tuning &b)
+{
+    return a.load_factor == b.load_factor && a.probe_tile == b.probe_tile && a.build_tile == b.build_tile &&
+           a.init_tile == b.init_tile && a.lag == b.lag && a.fanout == b.fanout;
+}
+
+// The points one sweep of axis `axis` visits from `base`.
+std::vector<gq_tuning> axis_points(const gq_tuning &base, int axis)
 {
     std::vector<gq_tuning> v;
-    const double lfs[] = {0.5, 0.7};
-    const int tiles[] = {4096, 16384, 65536};
-    const int lags[] = {1, 4};
-    for (double lf : lfs)
-        for (int pt : tiles)
-            for (int lag : lags) {
-                gq_tuning t = gq_default_tuning();
-                t.load_factor = lf;
-                t.probe_tile = pt;
-                t.lag = lag;
-                v.push_back(t);
-            }
+    auto add = [&](gq_tuning t) { v.push_back(t); };
+    gq_tuning t = base;
+    switch (axis) {
+    case 0: for (double x : TUNE_LF) { t.load_factor = x; add(t); } break;
+    case 1: for (int x : TUNE_TILE) { t.probe_tile = x; add(t); } break;
+    case 2: for (int x : TUNE_LAG) { t.lag = x; add(t); } break;
+    case 3: for (int x : TUNE_FANOUT) { t.fanout = x; add(t); } break;
+    default: for (int x : TUNE_BUILD) { t.build_tile = x; add(t); } break;
+    }
     return v;
 }
+constexpr int TUNE_AXES = 5;
 
 bool cache_lookup(const char *path, uint64_t sig, gq_tuning *t, double *ms)
 {
@@ -808,8 +870,8 @@ bool cache_lookup(const char *path, uint64_t sig, gq_tuning *t, double *ms)
         unsigned long long s;
         gq_tuning x = gq_default_tuning();
         double m;
-        if (sscanf(line, "%llx %lf %d %d %d %d %lf", &s, &x.load_factor, &x.probe_tile, &x.build_tile, &x.init_tile,
-                   &x.lag, &m) == 7 &&
+        if (sscanf(line, "%llx %lf %d %d %d %d %d %lf", &s, &x.load_factor, &x.probe_tile, &x.build_tile,
+                   &x.init_tile, &x.lag, &x.fanout, &m) == 8 &&
             s == sig && valid_tuning(x)) {
             *t = x;
             *ms = m;
@@ -825,8 +887,8 @@ void cache_store(const char *path, uint64_t sig, const gq_tuning &t, double ms)
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%llx %.3f %d %d %d %d %.4f\n", static_cast<unsigned long long>(sig), t.load_factor, t.probe_tile,
-            t.build_tile, t.init_tile, t.lag, ms);
+    fprintf(f, "%llx %.3f %d %d %d %d %d %.4f\n", static_cast<unsigned long long>(sig), t.load_factor, t.probe_tile,
+            t.build_tile, t.init_tile, t.lag, t.fanout, ms);
     fclose(f);
 }
 
@@ -836,8 +898,17 @@ extern "C" {
 
 size_t gq_batch_autotune_workspace_bytes(const gq_instance *inst, int n_inst)
 {
+    // the largest point: the lowest load factor (largest tables) with the
+    // longest segment table (smallest tiles, widest fan-out, smallest builds)
     size_t best = 0;
-    for (const gq_tuning &t : candidates()) best = std::max(best, gq_batch_workspace_bytes(inst, n_inst, &t));
+    for (double lf : TUNE_LF) {
+        gq_tuning t = tune_start();
+        t.load_factor = lf;
+        t.probe_tile = TUNE_TILE[0];
+        t.fanout = TUNE_FANOUT[sizeof(TUNE_FANOUT) / sizeof(TUNE_FANOUT[0]) - 1];
+        t.build_tile = TUNE_BUILD[0];
+        best = std::max(best, gq_batch_workspace_bytes(inst, n_inst, &t));
+    }
     return best;
 }
 
@@ -852,22 +923,39 @@ gq_status gq_batch_autotune(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
     hipEvent_t e0, e1;
     GQ_CHECK_HIP(ctx, hipEventCreate(&e0));
     GQ_CHECK_HIP(ctx, hipEventCreate(&e1));
-    double bms = 1e30;
-    gq_tuning bt = gq_default_tuning();
     gq_status rc = GQ_OK;
-    for (const gq_tuning &t : candidates()) {
-        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream);   // warm-up
-        if (rc != GQ_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { rc = GQ_ERR_HIP; break; }
-        rc = gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream);
-        if (rc != GQ_OK) break;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = GQ_ERR_HIP; break; }
+    // one warm-up run, then the time of one run, on the caller's stream
+    auto time_of = [&](const gq_tuning &t, double *ms_out) -> gq_status {
+        GQ_TRY(gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream));
+        GQ_CHECK_HIP(ctx, hipEventRecord(e0, s));
+        GQ_TRY(gq_batch_join_agg(ctx, inst, n_inst, &t, nullptr, ws, ws_bytes, stream));
+        GQ_CHECK_HIP(ctx, hipEventRecord(e1, s));
+        GQ_CHECK_HIP(ctx, hipEventSynchronize(e1));
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = GQ_ERR_HIP; break; }
-        if (ms < bms) {
-            bms = ms;
-            bt = t;
+        GQ_CHECK_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms;
+        return GQ_OK;
+    };
+    gq_tuning bt = tune_start();
+    double bms = 1e30;
+    rc = time_of(bt, &bms);
+    for (int round = 0; round < TUNE_ROUNDS && rc == GQ_OK; ++round) {
+        bool moved = false;
+        for (int axis = 0; axis < TUNE_AXES && rc == GQ_OK; ++axis) {
+            const gq_tuning from = bt;
+            for (const gq_tuning &t : axis_points(from, axis)) {
+                if (same_tuning(t, from)) continue;
+                double ms = 0.0;
+                rc = time_of(t, &ms);
+                if (rc != GQ_OK) break;
+                if (ms < bms) {
+                    bms = ms;
+                    bt = t;
+                    moved = true;
+                }
+            }
         }
+        if (!moved) break;                               // a full round changed nothing
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

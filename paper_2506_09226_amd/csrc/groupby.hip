@@ -24,6 +24,7 @@
 // retries the same slot on its next pass of a wave-uniform loop, so the
 // claiming lane always finishes first.
 #include <algorithm>
+#include <cstdlib>
 
 #include "gq_device.h"
 #include "gq_internal.h"
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 // has an entry there folds it in when it writes the group out and marks the
 // entry taken (state 3).  With no wide rows the side list stays empty.
 constexpr int GB_MAX_P = 1024;                      // buckets of the tile-staged scatter
-constexpr int GB_MAX_P_WIDE = 8192;                 // buckets of the chunked direct scatter
+constexpr int GB_MAX_P_WIDE = 8192;                 // buckets of the two-level scatter
 constexpr int64_t GB_CUS = 256;                     // compute units of the MI355X
 constexpr int GB_BUCKET_ITEMS = 4;
 
@@ -575,6 +576,19 @@ GQ_DEV void read_words(const uint64_t *__restrict__ recs, int64_t i, int64_t &k6
         k32 = K32 ? static_cast<int32_t>(static_cast<uint32_t>(b)) : 0;
         qty = static_cast<int32_t>(static_cast<uint32_t>(b >> 32));
         rev = static_cast<int64_t>(p[2]);
+    }
+}
+
+// The key of a record held in registers (the word layout of make_words).
+template <bool K64, bool K32>
+GQ_DEV void key_of_words(const uint64_t *w, int64_t &k64, int32_t &k32)
+{
+    if constexpr (!K64) {
+        k64 = 0;
+        k32 = static_cast<int32_t>(static_cast<uint32_t>(w[0]));
+    } else {
+        k64 = static_cast<int64_t>(w[0]);
+        k32 = K32 ? static_cast<int32_t>(static_cast<uint32_t>(w[1])) : 0;
     }
 }
 
@@ -793,73 +807,186 @@ __global__ __launch_bounds__(256) void gb_side_kernel(gb_args a, const uint32_t 
     }
 }
 
-// Scatter for large fan-outs (more buckets than a tile has rows): workgroup
-// c walks its chunk of rows and appends each row's record at its bucket's
-// cursor (an LDS atomic), starting from the chunk's offset gofs[c * P + b].
-// A bucket's rows from one chunk stay contiguous, so consecutive records of
-// a bucket fill whole cache lines over the walk.
-template <bool K64, bool K32>
-__global__ __launch_bounds__(GB_THREADS) void gb_scatter_wide_kernel(gb_args a, int P, int64_t chunk_rows,
-                                                                     const uint32_t *__restrict__ gofs,
-                                                                     uint64_t *__restrict__ recs,
-                                                                     uint32_t *__restrict__ side, uint32_t *side_cnt)
+// Large fan-outs (P > GB_MAX_P buckets, up to GB_MAX_P_WIDE) in two levels,
+// each a tile-staged scatter with runs long enough to fill cache lines:
+//   level 1  the rows go to P1 = GB_P1 super-buckets (the scatter above, with
+//            P1 buckets): super-bucket s = the buckets [s P2, (s + 1) P2) of
+//            the full fan-out P = P1 P2, since floor(floor(x P1 P2) / P2) =
+//            floor(x P1) for the scaled hash x in [0, 1);
+//   level 2  each super-bucket's records are cut into tiles of GB_T2 records
+//            (a tile never straddles two super-buckets), every tile is counted
+//            by sub-bucket, a per-super-bucket column scan gives each (tile,
+//            sub-bucket) run its place, and the tile is staged in LDS by
+//            sub-bucket and written out as runs.
+// The bucket pass then reads buckets b = s P2 + sub as usual.
+constexpr int GB_P1 = 128;                          // super-buckets of level 1
+constexpr int GB_T2 = 2048;                         // records per level-2 tile
+constexpr int GB_MAX_P2 = GB_MAX_P_WIDE / GB_P1;    // 64
+
+// Level-2 tiles of each super-bucket: tpre[s] = tiles before super-bucket s,
+// tpre[P1] = all tiles.  One workgroup of 256 threads (P1 <= 256).
+__global__ __launch_bounds__(256) void gb_tiles2_kernel(const uint32_t *__restrict__ startA, int P1,
+                                                        uint32_t *__restrict__ tpre)
 {
-    constexpr int ITEMS = gb_fmt<K64, K32>::ITEMS;
-    constexpr int TILE = gb_fmt<K64, K32>::TILE;
-    constexpr int W = gb_fmt<K64, K32>::WORDS;
-    __shared__ uint32_t cursor[GB_MAX_P_WIDE];
-    // each XCD takes one contiguous range of chunks, so the runs that
-    // neighbouring chunks append to a bucket meet in one L2
-    const uint32_t chunk = gq_xcd_tile(blockIdx.x, gridDim.x);
-    for (int b = threadIdx.x; b < P; b += GB_THREADS) cursor[b] = gofs[static_cast<int64_t>(chunk) * P + b];
+    __shared__ uint32_t scan_smem[256 / 64];
+    const int sb = threadIdx.x;
+    uint32_t nt = 0;
+    if (sb < P1) nt = (startA[sb + 1] - startA[sb] + GB_T2 - 1) / GB_T2;
+    uint32_t total;
+    const uint32_t excl = gq_block_exclusive_scan<256>(nt, &total, scan_smem);
+    if (sb < P1) tpre[sb] = excl;
+    if (threadIdx.x == 0) tpre[P1] = total;
+}
+
+// The super-bucket of level-2 tile g: the last s with tpre[s] <= g.
+GQ_DEV int gb_super_of(const uint32_t *tpre, int P1, uint32_t g)
+{
+    int lo = 0, hi = P1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tpre[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Per level-2 tile: its records counted by sub-bucket -> hist2[g * P2 + sub].
+// Grid: an upper bound on the tile count; surplus workgroups exit.
+template <bool K64, bool K32>
+__global__ __launch_bounds__(GB_THREADS) void gb_hist2_kernel(const uint64_t *__restrict__ recs1,
+                                                              const uint32_t *__restrict__ startA,
+                                                              const uint32_t *__restrict__ tpre, int P1, int P,
+                                                              int P2, uint32_t *__restrict__ hist2)
+{
+    __shared__ uint32_t h[GB_MAX_P2];
+    const uint32_t g = blockIdx.x;
+    if (g >= tpre[P1]) return;                          // same value for the whole workgroup
+    for (int i = threadIdx.x; i < P2; i += GB_THREADS) h[i] = 0;
     __syncthreads();
-    const int64_t n = eff_n(a.n_bound, a.n_dev);
-    const int64_t c0 = static_cast<int64_t>(chunk) * chunk_rows;
-    const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
-    for (int64_t base = c0; base < c1; base += TILE) {
-        // all loads of the thread's rows first (row ids, then keys and values),
-        // so that they are in flight together
-        int64_t vr[ITEMS];
-        bool keep[ITEMS];
-#pragma unroll
-        for (int c = 0; c < ITEMS; ++c) {
-            const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            keep[c] = j < c1;
-            vr[c] = keep[c] ? value_row(a, j) : 0;
+    const int sb = gb_super_of(tpre, P1, g);
+    const int64_t r0 = static_cast<int64_t>(startA[sb]) + static_cast<int64_t>(g - tpre[sb]) * GB_T2;
+    const int64_t r1 = r0 + GB_T2 < static_cast<int64_t>(startA[sb + 1]) ? r0 + GB_T2 : startA[sb + 1];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += GB_THREADS) {
+        int64_t k64, q, rv;
+        int32_t k32;
+        read_words<K64, K32>(recs1, i, k64, k32, q, rv);
+        const uint32_t b = gb_bucket(gb_hash(k64, k32), P);
+        atomicAdd(&h[b - static_cast<uint32_t>(sb) * P2], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < P2; i += GB_THREADS) hist2[static_cast<int64_t>(g) * P2 + i] = h[i];
+}
+
+// One workgroup per super-bucket s: the counts of its tiles become the output
+// position of every (tile, sub-bucket) run (in place), and start[s P2 + sub]
+// the start of every bucket (start[P] = all records).  Thread (q, col) sums,
+// then writes, column col over the q-th quarter of s's tiles.
+__global__ __launch_bounds__(256) void gb_scan2_kernel(uint32_t *__restrict__ hist2,
+                                                       const uint32_t *__restrict__ startA,
+                                                       const uint32_t *__restrict__ tpre, int P1, int P2,
+                                                       uint32_t *__restrict__ start)
+{
+    __shared__ uint32_t part[4][GB_MAX_P2];
+    __shared__ uint32_t colbase[GB_MAX_P2];
+    const int sb = blockIdx.x;
+    const int col = threadIdx.x & (GB_MAX_P2 - 1), q = threadIdx.x / GB_MAX_P2;
+    const int64_t t0 = tpre[sb], nt = static_cast<int64_t>(tpre[sb + 1]) - t0;
+    const int64_t a = t0 + nt * q / 4, b = t0 + nt * (q + 1) / 4;
+    uint32_t sum = 0;
+    if (col < P2) {
+#pragma unroll 8
+        for (int64_t t = a; t < b; ++t) sum += hist2[t * P2 + col];
+    }
+    part[q][col] = sum;
+    __syncthreads();
+    if (threadIdx.x < GB_MAX_P2) {                      // one wave: the columns' totals, scanned
+        const uint32_t tot = col < P2 ? part[0][col] + part[1][col] + part[2][col] + part[3][col] : 0u;
+        const uint32_t inc = gq_wave_inclusive_scan(tot);
+        const uint32_t base = startA[sb] + inc - tot;
+        colbase[col] = base;
+        if (col < P2) start[sb * P2 + col] = base;
+        if (sb == P1 - 1 && col == 0) start[P1 * P2] = startA[P1];
+    }
+    __syncthreads();
+    if (col < P2) {
+        uint32_t run = colbase[col];
+        for (int p = 0; p < q; ++p) run += part[p][col];
+        for (int64_t t = a; t < b; ++t) {
+            const uint32_t c = hist2[t * P2 + col];
+            hist2[t * P2 + col] = run;
+            run += c;
         }
-        if (a.filter) {
+    }
+}
+
+// Per level-2 tile: its records ranked by sub-bucket (LDS atomics; the order
+// inside a bucket does not matter to sums), staged in LDS in sub-bucket
+// order and written out as runs at the positions the scan gave.
+template <bool K64, bool K32>
+__global__ __launch_bounds__(GB_THREADS) void gb_scatter2_kernel(const uint64_t *__restrict__ recs1,
+                                                                 const uint32_t *__restrict__ startA,
+                                                                 const uint32_t *__restrict__ tpre,
+                                                                 const uint32_t *__restrict__ off2, int P1, int P,
+                                                                 int P2, uint64_t *__restrict__ recs)
+{
+    constexpr int W = gb_fmt<K64, K32>::WORDS;
+    constexpr int ITEMS = GB_T2 / GB_THREADS;
+    __shared__ uint32_t cnt[GB_MAX_P2];
+    __shared__ uint32_t lstart[GB_MAX_P2];
+    __shared__ uint32_t delta[GB_MAX_P2];
+    __shared__ uint8_t lsub[GB_T2];
+    __shared__ uint64_t stage[GB_T2 * W];
+    const uint32_t g = blockIdx.x;
+    if (g >= tpre[P1]) return;                          // same value for the whole workgroup
+    const int sb = gb_super_of(tpre, P1, g);
+    const int64_t r0 = static_cast<int64_t>(startA[sb]) + static_cast<int64_t>(g - tpre[sb]) * GB_T2;
+    const int64_t rem = static_cast<int64_t>(startA[sb + 1]) - r0;
+    const int rows = static_cast<int>(rem < GB_T2 ? rem : GB_T2);
+    for (int i = threadIdx.x; i < P2; i += GB_THREADS) cnt[i] = 0;
+    uint64_t w[ITEMS][W];
+    uint32_t pos[ITEMS];
 #pragma unroll
-            for (int c = 0; c < ITEMS; ++c) keep[c] = keep[c] && row_pass(a, vr[c]);
+    for (int c = 0; c < ITEMS; ++c) {
+        const int i = c * GB_THREADS + threadIdx.x;
+#pragma unroll
+        for (int x = 0; x < W; ++x) w[c][x] = i < rows ? recs1[(r0 + i) * W + x] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        const int i = c * GB_THREADS + threadIdx.x;
+        if (i < rows) {
+            int64_t k64;
+            int32_t k32;
+            key_of_words<K64, K32>(w[c], k64, k32);
+            const uint32_t sub = gb_bucket(gb_hash(k64, k32), P) - static_cast<uint32_t>(sb) * P2;
+            pos[c] = (sub << 16) | atomicAdd(&cnt[sub], 1u);
         }
-        int64_t k64[ITEMS], qv[ITEMS], pv[ITEMS], dv[ITEMS];
-        int32_t k32[ITEMS];
+    }
+    __syncthreads();
+    if (threadIdx.x < GB_MAX_P2) {
+        const uint32_t x = threadIdx.x < static_cast<uint32_t>(P2) ? cnt[threadIdx.x] : 0u;
+        const uint32_t ex = gq_wave_inclusive_scan(x) - x;
+        lstart[threadIdx.x] = ex;
+        if (threadIdx.x < static_cast<uint32_t>(P2))
+            delta[threadIdx.x] = off2[static_cast<int64_t>(g) * P2 + threadIdx.x] - ex;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int c = 0; c < ITEMS; ++c) {
-            const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            k64[c] = qv[c] = pv[c] = dv[c] = 0;
-            k32[c] = 0;
-            if (keep[c]) {
-                k64[c] = K64 ? a.key64[a.key64_by_rowid ? vr[c] : j] : 0;
-                k32[c] = K32 ? a.key32[a.key32_by_rowid ? vr[c] : j] : 0;
-                qv[c] = a.qty[vr[c]];
-                pv[c] = a.price[vr[c]];
-                dv[c] = a.disc[vr[c]];
-            }
+    for (int c = 0; c < ITEMS; ++c) {
+        const int i = c * GB_THREADS + threadIdx.x;
+        if (i < rows) {
+            const uint32_t sub = pos[c] >> 16;
+            const uint32_t qd = lstart[sub] + (pos[c] & 0xffffu);
+            lsub[qd] = static_cast<uint8_t>(sub);
+#pragma unroll
+            for (int x = 0; x < W; ++x) stage[qd * W + x] = w[c][x];
         }
-#pragma unroll
-        for (int c = 0; c < ITEMS; ++c) {
-            if (!keep[c]) continue;
-            const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            const gq_i128 rev = gq_revenue(pv[c], a.rev_scale, dv[c]);
-            const bool nar = is_narrow(qv[c], rev);
-            if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
-            uint64_t w[W];
-            make_words<K64, K32>(w, k64[c], k32[c], nar ? static_cast<int32_t>(qv[c]) : 0,
-                                 nar ? static_cast<int64_t>(rev.lo) : 0);
-            const uint32_t pos = atomicAdd(&cursor[gb_bucket(gb_hash(k64[c], k32[c]), P)], 1u);
-#pragma unroll
-            for (int x = 0; x < W; ++x) recs[static_cast<int64_t>(pos) * W + x] = w[x];
-        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * W; e += GB_THREADS) {
+        const int qd = e / W, x = e - qd * W;
+        recs[(static_cast<int64_t>(qd) + delta[lsub[qd]]) * W + x] = stage[e];
     }
 }
 
@@ -1069,14 +1196,26 @@ uint64_t next_pow2(uint64_t x)
 struct gb_plan {
     bool small;
     int P;                  // buckets of the large path
-    bool wide;              // P > GB_MAX_P: chunked hist and direct scatter
-    int64_t ntiles;         // hist/scatter workgroups (tiles, or chunks when wide)
+    bool wide;              // P > GB_MAX_P: two levels (GB_P1 super-buckets, then P / GB_P1 each)
+    int P2;                 // sub-buckets per super-bucket (wide)
+    int64_t tiles2;         // level-2 tiles, an upper bound (wide)
+    int64_t ntiles;         // hist/scatter tiles (of level 1 when wide)
     int64_t chunk_rows;     // rows per hist/scatter workgroup
     int words;              // 8-byte words per partitioned record
     uint64_t gslots;
     int64_t bucket_chunk;   // rows per workgroup of a split bucket
     int64_t bucket_grid;    // bucket-pass workgroups: P plus the most extra chunks n rows can need
 };
+
+int groupby_fill_percent()
+{
+    static const int v = [] {
+        const char *e = getenv("GQ_GROUPBY_FILL");
+        const int x = e ? atoi(e) : 40;
+        return (x >= 10 && x <= 90) ? x : 40;
+    }();
+    return v;
+}
 
 gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
 {
@@ -1091,8 +1230,9 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
     if (!pl.small) {
         // about 40% of a bucket's LDS table for the expected groups: the
         // bucket pass waits on the longest probe chain of 64 lanes, so short
-        // chains pay for the extra buckets
-        const int64_t per_bucket = (k64 ? 3072 : 4096) * 4 / 10;
+        // chains pay for the extra buckets (GQ_GROUPBY_FILL=<percent>, 10..90,
+        // overrides it for measurements)
+        const int64_t per_bucket = (k64 ? 3072 : 4096) * groupby_fill_percent() / 100;
         int64_t P = (max_groups + per_bucket - 1) / per_bucket;
         // one 1024-thread workgroup per bucket and one per CU at a time: a
         // whole number of rounds over the CUs leaves no idle tail
@@ -1105,11 +1245,9 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
         pl.bucket_chunk = std::max<int64_t>(4 * mean, 65536);
         pl.bucket_chunk = (pl.bucket_chunk + 4095) / 4096 * 4096;
         pl.bucket_grid = pl.P + n / pl.bucket_chunk;
-        if (pl.wide) {                      // 2048 chunks of whole tiles
-            const int64_t tiles = pl.ntiles;
-            const int64_t per = (tiles + 2047) / 2048;
-            pl.chunk_rows = per * tile;
-            pl.ntiles = n > 0 ? (n + pl.chunk_rows - 1) / pl.chunk_rows : 1;
+        if (pl.wide) {                      // P is a multiple of GB_CUS, so of GB_P1
+            pl.P2 = pl.P / GB_P1;
+            pl.tiles2 = (n + GB_T2 - 1) / GB_T2 + GB_P1;
         }
     }
     return pl;
@@ -1124,6 +1262,10 @@ struct gb_ws {
     void *scan_ws;
     uint64_t *recs;         // partitioned rows, narrow records
     uint32_t *side;         // row indices of wide rows
+    uint32_t *startA;       // two levels: super-bucket starts (level 1)
+    uint32_t *tpre;         //   level-2 tiles before each super-bucket
+    uint32_t *hist2;        //   level-2 counts, then run positions, per (tile, sub-bucket)
+    uint64_t *recs1;        //   level-1 records, in super-bucket order
     size_t zero_bytes;      // prefix of the workspace to clear (table, side count)
 };
 
@@ -1145,12 +1287,19 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     w.g.mask = S - 1;
     if (!pl.small) {
         const size_t rows = static_cast<size_t>(n > 0 ? n : 1);
-        w.hist = c.take<uint32_t>(static_cast<size_t>(pl.ntiles) * static_cast<size_t>(pl.P));
+        const int P1 = pl.wide ? GB_P1 : pl.P;              // buckets of the tile-staged scatter
+        w.hist = c.take<uint32_t>(static_cast<size_t>(pl.ntiles) * static_cast<size_t>(P1));
         w.start = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
         w.cstart = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
-        w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, pl.P));
+        w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, P1));
         w.recs = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
         w.side = c.take<uint32_t>(rows);
+        if (pl.wide) {
+            w.startA = c.take<uint32_t>(GB_P1 + 1);
+            w.tpre = c.take<uint32_t>(GB_P1 + 1);
+            w.hist2 = c.take<uint32_t>(static_cast<size_t>(pl.tiles2) * static_cast<size_t>(pl.P2));
+            w.recs1 = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
+        }
     }
     return w;
 }
@@ -1172,28 +1321,36 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                          w.g, out, ctx->status_dev);
     }
     const uint32_t grid = static_cast<uint32_t>(pl.ntiles);
-    if (pl.wide)
-        GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P_WIDE>, dim3(grid), dim3(GB_THREADS),
-                         0, s, a, pl.P, pl.chunk_rows, w.hist));
-    else
-        GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P>, dim3(grid), dim3(GB_THREADS), 0,
-                         s, a, pl.P, pl.chunk_rows, w.hist));
+    const int P1 = pl.wide ? GB_P1 : pl.P;              // buckets of the tile-staged scatter
+    uint32_t *start1 = pl.wide ? w.startA : w.start;
+    uint64_t *recs1 = pl.wide ? w.recs1 : w.recs;
+    GQ_TRY(gq_launch(ctx, "gq_groupby_hist", gb_hist_kernel<K64, K32, GB_MAX_P>, dim3(grid), dim3(GB_THREADS), 0, s,
+                     a, P1, pl.chunk_rows, w.hist));
     const gq_tile_count live{a.n_dev, a.n_bound, pl.chunk_rows};     // tiles past the device row count are idle
-    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, pl.P, w.start, w.scan_ws, s, "gq_groupby_scan", &live));
-    if (pl.wide)
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_wide_kernel<K64, K32>, dim3(grid), dim3(GB_THREADS), 0,
-                         s, a, pl.P, pl.chunk_rows, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
-                         w.side_cnt));
-    else {
-        // XCD x scatters the x-th eighth of the tiles with the workgroups b of
-        // b mod 8 = x, so the grid is a whole number of rounds over the eight
-        // XCDs (at least one workgroup each, even for fewer than 8 tiles); a
-        // workgroup whose range is empty exits at once
-        int64_t sgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3));
-        sgrid = (sgrid + GQ_NUM_XCD - 1) / GQ_NUM_XCD * GQ_NUM_XCD;
-        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(static_cast<uint32_t>(sgrid)),
-                         dim3(GB_THREADS), 0, s, a, pl.P, static_cast<const uint32_t *>(w.hist), w.recs, w.side,
-                         w.side_cnt, w.side_cnt + 32));
+    GQ_TRY(gq_tile_offsets(ctx, w.hist, pl.ntiles, P1, start1, w.scan_ws, s, "gq_groupby_scan", &live));
+    // XCD x scatters the x-th eighth of the tiles with the workgroups b of
+    // b mod 8 = x, so the grid is a whole number of rounds over the eight
+    // XCDs (at least one workgroup each, even for fewer than 8 tiles); a
+    // workgroup whose range is empty exits at once
+    int64_t sgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3));
+    sgrid = (sgrid + GQ_NUM_XCD - 1) / GQ_NUM_XCD * GQ_NUM_XCD;
+    GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(static_cast<uint32_t>(sgrid)),
+                     dim3(GB_THREADS), 0, s, a, P1, static_cast<const uint32_t *>(w.hist), recs1, w.side,
+                     w.side_cnt, w.side_cnt + 32));
+    if (pl.wide) {                                      // level 2: each super-bucket by its sub-buckets
+        GQ_TRY(gq_launch(ctx, "gq_groupby_tiles2", gb_tiles2_kernel, dim3(1), dim3(256), 0, s,
+                         static_cast<const uint32_t *>(w.startA), GB_P1, w.tpre));
+        const uint32_t g2 = static_cast<uint32_t>(pl.tiles2);
+        GQ_TRY(gq_launch(ctx, "gq_groupby_hist2", gb_hist2_kernel<K64, K32>, dim3(g2), dim3(GB_THREADS), 0, s,
+                         static_cast<const uint64_t *>(w.recs1), static_cast<const uint32_t *>(w.startA),
+                         static_cast<const uint32_t *>(w.tpre), GB_P1, pl.P, pl.P2, w.hist2));
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scan2", gb_scan2_kernel, dim3(GB_P1), dim3(256), 0, s, w.hist2,
+                         static_cast<const uint32_t *>(w.startA), static_cast<const uint32_t *>(w.tpre), GB_P1, pl.P2,
+                         w.start));
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter2", gb_scatter2_kernel<K64, K32>, dim3(g2), dim3(GB_THREADS), 0, s,
+                         static_cast<const uint64_t *>(w.recs1), static_cast<const uint32_t *>(w.startA),
+                         static_cast<const uint32_t *>(w.tpre), static_cast<const uint32_t *>(w.hist2), GB_P1, pl.P,
+                         pl.P2, w.recs));
     }
     GQ_TRY(gq_launch(ctx, "gq_groupby_side", gb_side_kernel<K64, K32>, dim3(64), dim3(256), 0, s, a,
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,

@@ -145,12 +145,18 @@ __global__ __launch_bounds__(256) void jt_region_bounds_kernel(const int64_t *__
 
 // A persistent grid walks the regions; the barriers between a region's phases
 // order LDS only, so one region's table stores drain while the next region's
-// keys load.
-__global__ __launch_bounds__(256) void jt_region_kernel(void *table, int L, const int64_t *__restrict__ keys,
-                                                        const int32_t *__restrict__ pay,
-                                                        const int64_t *__restrict__ roff, int64_t nregions,
-                                                        int64_t *__restrict__ ovf_key, int32_t *__restrict__ ovf_pay,
-                                                        uint32_t *ovf_cnt, int64_t ovf_cap, uint32_t *status)
+// keys load.  A thread's keys of a region (up to JR_BATCH, a region holding
+// about 2048 * load factor keys) are loaded together, and the next region's
+// are loaded before the current region is written out.
+constexpr int JR_THREADS = 256;
+constexpr int JR_BATCH = 8;                          // keys per thread loaded together
+
+__global__ __launch_bounds__(JR_THREADS) void jt_region_kernel(void *table, int L, const int64_t *__restrict__ keys,
+                                                               const int32_t *__restrict__ pay,
+                                                               const int64_t *__restrict__ roff, int64_t nregions,
+                                                               int64_t *__restrict__ ovf_key,
+                                                               int32_t *__restrict__ ovf_pay, uint32_t *ovf_cnt,
+                                                               int64_t ovf_cap, uint32_t *status)
 {
     __shared__ unsigned long long sk[JR_SLOTS];
     __shared__ int32_t sp[JR_SLOTS];
@@ -161,49 +167,79 @@ __global__ __launch_bounds__(256) void jt_region_kernel(void *table, int L, cons
         h->unused = 0;
         h->slots = 1ull << L;
     }
-    for (int64_t region = blockIdx.x; region < nregions; region += gridDim.x) {
+    int64_t k[JR_BATCH];
+    int32_t p[JR_BATCH];
+    bool v[JR_BATCH];
+    auto load_batch = [&](int64_t i0, int64_t end) {
+#pragma unroll
+        for (int c = 0; c < JR_BATCH; ++c) {
+            const int64_t i = i0 + c * JR_THREADS + threadIdx.x;
+            v[c] = i < end;
+            k[c] = v[c] ? keys[i] : 0;
+            p[c] = v[c] ? pay[i] : 0;
+        }
+    };
+    int64_t region = blockIdx.x;
+    int64_t r0 = 0, r1 = 0;
+    if (region < nregions) {
+        r0 = roff[region];
+        r1 = roff[region + 1];
+        load_batch(r0, r1);
+    }
+    for (; region < nregions; region += gridDim.x) {
         gq_lds_barrier();                             // the previous region is read out of LDS
-        for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+        for (int j = threadIdx.x; j < JR_SLOTS; j += JR_THREADS) {
             sk[j] = static_cast<unsigned long long>(JT_EMPTY);
             sp[j] = 0;
         }
         gq_lds_barrier();
-        const int64_t r0 = roff[region], r1 = roff[region + 1];
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-            const int64_t k = keys[i];
-            const int32_t p = pay[i];
-            if (k == JT_EMPTY) {
-                gq_raise(status, GQ_ERR_INVALID_KEY);
-                continue;
-            }
-            uint32_t loc = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k)) >> (64 - L)) & (JR_SLOTS - 1);
-            while (true) {
-                const unsigned long long prev =
-                    atomicCAS(&sk[loc], static_cast<unsigned long long>(JT_EMPTY), static_cast<unsigned long long>(k));
-                if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
-                    sp[loc] = p;
-                    break;
+        for (int64_t i0 = r0;;) {
+#pragma unroll
+            for (int c = 0; c < JR_BATCH; ++c) {
+                if (!v[c]) continue;
+                if (k[c] == JT_EMPTY) {
+                    gq_raise(status, GQ_ERR_INVALID_KEY);
+                    continue;
                 }
-                if (prev == static_cast<unsigned long long>(k)) {
-                    gq_raise(status, GQ_ERR_DUPLICATE_KEY);
-                    break;
-                }
-                if (++loc == JR_SLOTS) {                 // continue in the next region, later
-                    const uint32_t idx = atomicAdd(ovf_cnt, 1u);
-                    if (idx < ovf_cap) {
-                        ovf_key[idx] = k;
-                        ovf_pay[idx] = p;
-                    } else {
-                        gq_raise(status, GQ_ERR_CAPACITY);
+                uint32_t loc =
+                    static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - L)) & (JR_SLOTS - 1);
+                while (true) {
+                    const unsigned long long prev = atomicCAS(&sk[loc], static_cast<unsigned long long>(JT_EMPTY),
+                                                              static_cast<unsigned long long>(k[c]));
+                    if (prev == static_cast<unsigned long long>(JT_EMPTY)) {
+                        sp[loc] = p[c];
+                        break;
                     }
-                    break;
+                    if (prev == static_cast<unsigned long long>(k[c])) {
+                        gq_raise(status, GQ_ERR_DUPLICATE_KEY);
+                        break;
+                    }
+                    if (++loc == JR_SLOTS) {             // continue in the next region, later
+                        const uint32_t idx = atomicAdd(ovf_cnt, 1u);
+                        if (idx < ovf_cap) {
+                            ovf_key[idx] = k[c];
+                            ovf_pay[idx] = p[c];
+                        } else {
+                            gq_raise(status, GQ_ERR_CAPACITY);
+                        }
+                        break;
+                    }
                 }
             }
+            i0 += JR_THREADS * JR_BATCH;
+            if (i0 >= r1) break;
+            load_batch(i0, r1);                          // a region with more keys than one batch
+        }
+        const int64_t next = region + gridDim.x;         // the next region's keys: in flight meanwhile
+        if (next < nregions) {
+            r0 = roff[next];
+            r1 = roff[next + 1];
+            load_batch(r0, r1);
         }
         gq_lds_barrier();
         jt_slot *slots = reinterpret_cast<jt_slot *>(static_cast<char *>(table) + JT_HEADER) +
                          (static_cast<uint64_t>(region) << JR_BITS);
-        for (int j = threadIdx.x; j < JR_SLOTS; j += blockDim.x) {
+        for (int j = threadIdx.x; j < JR_SLOTS; j += JR_THREADS) {
             jt_slot e;
             e.key = static_cast<int64_t>(sk[j]);
             e.payload = sp[j];
@@ -324,7 +360,7 @@ gq_status region_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, 
                      0, s, static_cast<const int64_t *>(w.k2), m, g, w.roff));
     const int64_t nregions = int64_t(1) << g;
     const uint32_t rgrid = static_cast<uint32_t>(std::min<int64_t>(nregions, int64_t(ctx->num_cus) * 3));
-    GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(rgrid), dim3(256), 0, s, table, L,
+    GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(rgrid), dim3(JR_THREADS), 0, s, table, L,
                      static_cast<const int64_t *>(w.k2), static_cast<const int32_t *>(w.p2),
                      static_cast<const int64_t *>(w.roff), nregions, w.ovf_key, w.ovf_pay, w.ovf_cnt, w.ovf_cap,
                      ctx->status_dev));

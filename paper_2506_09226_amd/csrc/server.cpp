@@ -24,6 +24,7 @@
 #include "gq_device.h"
 #include "gq_internal.h"
 #include "gq_serve.h"
+#include "gq_serve_policy.h"
 
 namespace {
 
@@ -160,21 +161,24 @@ void gq_server::retire(slot_t &sl, hipError_t q)
     std::vector<pending> again;
     const auto now = clk::now();
     for (pending &p : sl.items) {
-        const bool agg = p.q.kind != GQ_QUERY_FILTER_TOPK;
-        if (st != GQ_OK && st != GQ_ERR_HIP && sl.items.size() > 1) {
-            p.solo = true;                       // whose error was it? run each alone
+        gq_retire_case rc{};
+        rc.batch_status = st;
+        rc.batch_queries = static_cast<int>(sl.items.size());
+        rc.aggregate = p.q.kind != GQ_QUERY_FILTER_TOPK;
+        rc.max_groups = p.q.max_groups;
+        rc.capacity = p.q.out.groups.capacity;
+        gq_serve_query doubled = p.q;
+        if (st == GQ_ERR_CAPACITY && rc.aggregate) {
+            doubled.max_groups = gq_doubled_groups(p.q.max_groups, rc.capacity);
+            rc.doubled_fits =
+                ((gq_serve_single_bytes(tables, doubled) + 255) & ~size_t(255)) <= (pool_bytes & ~size_t(255));
+        }
+        const gq_retire_action act = gq_retire_decide(rc);
+        if (act != gq_retire_action::complete) {
+            if (act == gq_retire_action::rerun_doubled) p.q = doubled;
+            p.solo = true;
             again.push_back(p);
             continue;
-        }
-        if (st == GQ_ERR_CAPACITY && agg && p.q.max_groups < p.q.out.groups.capacity) {
-            gq_serve_query x = p.q;
-            x.max_groups = std::min<int64_t>(2 * x.max_groups, x.out.groups.capacity);
-            if (((gq_serve_single_bytes(tables, x) + 255) & ~size_t(255)) <= (pool_bytes & ~size_t(255))) {
-                p.q = x;                         // it still fits the pool alone: run it again, larger
-                p.solo = true;
-                again.push_back(p);
-                continue;
-            }
         }
         done_state &d = states[p.ticket];
         d.done = true;

@@ -65,15 +65,16 @@ def test_batch_equals_oracle_and_plain(ctx, small_batch):
         _equal(_sorted(gp), e)
 
 
-@pytest.mark.parametrize("lf,tile,lag,build", [(0.5, 4096, 0, 256), (0.7, 16384, 3, 1024), (0.9, 8192, 1, 4096),
-                                               (0.3, 65536, 47, 256)])
-def test_batch_tunings_identical(ctx, small_batch, lf, tile, lag, build):
+@pytest.mark.parametrize("lf,tile,lag,build,fanout", [(0.5, 4096, 0, 256, 1), (0.7, 16384, 3, 1024, 4),
+                                                      (0.9, 8192, 1, 4096, 2), (0.3, 65536, 47, 256, 7),
+                                                      (0.5, 4096, 5, 1024, 64)])
+def test_batch_tunings_identical(ctx, small_batch, lf, tile, lag, build, fanout):
     spec, cols, layout = small_batch
     ref = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
     ref.run()
     b = BatchedJoinAgg(ctx, cols, layout, 0, spec.date_hi)
     t = gq.gq_default_tuning()
-    t.load_factor, t.probe_tile, t.lag, t.build_tile, t.init_tile = lf, tile, lag, build, 1024
+    t.load_factor, t.probe_tile, t.lag, t.build_tile, t.init_tile, t.fanout = lf, tile, lag, build, 1024, fanout
     b.tuning = t
     b.run()
     assert ctx.status() == gq.GQ_OK
