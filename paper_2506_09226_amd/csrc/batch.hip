@@ -173,6 +173,17 @@ GQ_DEV int lds_group(bt_lds &T, bool active, int32_t key)
     return found;
 }
 
+// one row into LDS slot s (revenue known to fit 64 bits)
+GQ_DEV void lds_add_row(bt_lds &T, int s, int64_t qty, int64_t rev)
+{
+    atomicAdd(&T.cnt[s], 1u);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[s]), static_cast<unsigned long long>(qty));
+    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[s]),
+              static_cast<unsigned long long>(static_cast<uint32_t>(static_cast<uint64_t>(rev))));
+    const int64_t high = rev >> 32;
+    if (high) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[s]), static_cast<unsigned long long>(high));
+}
+
 GQ_DEV gq_i128 split_total(uint64_t lo_sum, int64_t hi_sum)
 {
     const __int128 v = static_cast<__int128>(hi_sum) * (static_cast<__int128>(1) << 32) + static_cast<__int128>(lo_sum);
@@ -414,28 +425,7 @@ __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds
             const gq_i128 rev = hit[c] ? gq_revenue(pr[c], I.rev_scale, ds[c]) : gq_i128{0, 0};
             const bool fits = rev.hi == (static_cast<int64_t>(rev.lo) >> 63);
             const int slot = lds_group(T, hit[c] && fits, g[c]);
-            // An instance has few groups, so many lanes of a wave add to the
-            // same slot: the lanes of one slot are summed across the wave and
-            // added by one lane, slot after slot.  Revenues are summed split:
-            // the low 32 bits (unsigned) into lo[], the high 32 bits (signed)
-            // into hi[] (a slot's low-half sum over 64 lanes stays below 2^38).
-            bool mine = hit[c] && fits && slot >= 0;
-            for (uint64_t am = gq_ballot(mine); am; am = gq_ballot(mine)) {
-                const int lead = __builtin_ctzll(am);
-                const int sl = __builtin_amdgcn_readlane(slot, lead);
-                const bool in = mine && slot == sl;
-                const uint32_t cn = static_cast<uint32_t>(__popcll(gq_ballot(in)));
-                const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
-                const uint64_t lo = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(static_cast<uint32_t>(rev.lo)) : 0ull);
-                const int64_t hs = gq_wave_sum<int64_t>(in ? (static_cast<int64_t>(rev.lo) >> 32) : 0);
-                if (gq_lane() == lead) {
-                    atomicAdd(&T.cnt[sl], cn);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&T.sq[sl]), static_cast<unsigned long long>(sq));
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&T.lo[sl]), static_cast<unsigned long long>(lo));
-                    if (hs) atomicAdd(reinterpret_cast<unsigned long long *>(&T.hi[sl]), static_cast<unsigned long long>(hs));
-                }
-                mine = mine && !in;
-            }
+            if (hit[c] && fits && slot >= 0) lds_add_row(T, slot, q[c], static_cast<int64_t>(rev.lo));
             // a full LDS table or a revenue wider than 64 bits goes to the global table
             const bool spill = hit[c] && (!fits || slot < 0);
             const int64_t gs = global_group(I, spill, g[c], status);
