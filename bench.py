@@ -120,10 +120,15 @@ def _sysfs_clocks() -> dict:
     return out
 
 
+_NO_CLOCKS = False
+
+
 def gpu_clocks() -> dict:
     """Current GPU clocks, power and temperature as rocm-smi reports them,
     plus the sysfs DPM levels (read only; an error note if unavailable)."""
     import subprocess
+    if _NO_CLOCKS:
+        return {"skipped": "--no-clocks"}
     sysfs = _sysfs_clocks()
     try:
         r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showtemp", "--json"],
@@ -276,13 +281,17 @@ def main():
                     help="plain form: time replays of the step captured as one HIP graph (no per-kernel times)")
     ap.add_argument("--no-partition", action="store_true",
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
+    ap.add_argument("--no-clocks", action="store_true",
+                    help="record no GPU clocks (rocm-smi is not started; for runs under a profiler)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (3 times) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): this build runs the per-GPU hot path "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs the per-GPU hot path "
               f"on one GPU's share; the multi-GPU exchange is not built", file=sys.stderr)
         sys.exit(2)
+    global _NO_CLOCKS
+    _NO_CLOCKS = args.no_clocks
 
     if args.mode == "batch":
         out = bench_batch(args)
@@ -591,7 +600,7 @@ def bench_batch(args, sub: bool = False) -> dict:
            "frac_of_peak": round(by / (ms_b * 1e6) / HBM_PEAK_GBS, 4), "tuning": tun.as_dict(),
            "tuning_ms": round(tune_ms, 4),
            "tuning_search": "coordinate descent, 2 rounds: load factor {0.2,0.25,0.3,0.4,0.5,0.6,0.7}, probe tile "
-                            "{8K..512K} rows, lag {1..64}, probe fan-out {1,2,4,8,16}, build tile {1K..64K}",
+                            "{8K..512K} rows, lag {1..512}, probe fan-out {1,2,4,8,16}, build tile {1K..64K}",
            "plain_per_instance": {"ms": round(ms_p, 3), "GB/s": round(by / (ms_p * 1e6), 1),
                                   "launch_chains": len(layout), "steps": max(1, args.steps // 2)},
            "speedup_vs_plain": round(ms_p / ms_b, 3), "results_equal": same}

@@ -414,7 +414,7 @@ gq_status gq_batch_join_agg(gq_ctx *ctx, const gq_instance *inst, int n_inst, co
                             gq_status *inst_status_dev, void *ws, size_t ws_bytes, gq_stream stream);
 
 /* Autotuner: searches the tunings by coordinate descent over five axes
- * (load factor 0.2..0.7, probe tile 8K..512K rows, lag 1..64, probe fan-out
+ * (load factor 0.2..0.7, probe tile 8K..512K rows, lag 1..512, probe fan-out
  * 1..16, build tile 1K..64K keys): from a starting point each axis in turn is
  * swept with the others fixed, each point timed on the stream (a warm-up run,
  * then one timed run), and its best value kept, for up to two rounds.  The

@@ -813,7 +813,7 @@ uint64_t batch_signature(const gq_ctx *ctx, const gq_instance *in, int n)
 // values that win on the MI355X, so the winner lies inside the grid.
 constexpr double TUNE_LF[] = {0.2, 0.25, 0.3, 0.4, 0.5, 0.6, 0.7};
 constexpr int TUNE_TILE[] = {8192, 16384, 32768, 65536, 131072, 262144, 524288};
-constexpr int TUNE_LAG[] = {1, 2, 4, 8, 16, 32, 64};
+constexpr int TUNE_LAG[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512};
 constexpr int TUNE_FANOUT[] = {1, 2, 4, 8, 16};
 constexpr int TUNE_BUILD[] = {1024, 4096, 16384, 65536};
 constexpr int TUNE_ROUNDS = 2;

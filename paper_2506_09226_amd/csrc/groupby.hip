@@ -789,6 +789,170 @@ __global__ __launch_bounds__(GB_THREADS) void gb_scatter_kernel(gb_args a, int P
     }
 }
 
+// Scatter of 16-byte records (tables without key64) by regions: workgroup r
+// takes the r-th of gridDim.x contiguous ranges of hist chunks, and the
+// region's share of each bucket is one contiguous stretch of the output that
+// only this workgroup writes, front to back.  It therefore keeps the open end
+// of every stretch in LDS and writes whole aligned 128-byte lines (eight
+// records) only: per tile, each row takes the next place of its bucket with
+// an LDS atomic; a line that the tile completes is written from the line
+// buffer (its older records) and straight from the threads' registers (its
+// new ones), all within one phase of the tile, so its pieces meet in L2 and
+// leave it as one line; new records past the last complete line wait in the
+// buffer.  Only the first and last line of a region's stretch in a bucket
+// are written in part.  Row ids and direct keys are loaded two tiles ahead
+// and the value gathers one tile ahead, so a single workgroup per CU keeps
+// its loads in flight behind the LDS work (the barriers order LDS only).
+constexpr int GL_THREADS = 512;
+constexpr int GL_ITEMS = 8;
+constexpr int GL_TILE = GL_THREADS * GL_ITEMS;      // rows per tile
+constexpr int GL_LINE = 8;                          // records per written line (128 bytes)
+constexpr int64_t GL_CHUNK_ROWS = 8 * GL_TILE;      // rows per hist chunk
+
+template <bool K32>
+__global__ __launch_bounds__(GL_THREADS) void gb_scatter_lines_kernel(gb_args a, int P, int64_t chunk_rows,
+                                                                       const uint32_t *__restrict__ gofs,
+                                                                       uint4 *__restrict__ recs,
+                                                                       uint32_t *__restrict__ side, uint32_t *side_cnt)
+{
+    constexpr int GPER = GB_MAX_P / GL_THREADS;
+    constexpr uint32_t LMASK = ~static_cast<uint32_t>(GL_LINE - 1);
+    __shared__ uint4 lbuf[GB_MAX_P * GL_LINE];       // open line of each bucket, by position mod GL_LINE
+    __shared__ uint32_t cnt[GB_MAX_P];               // this tile's rows per bucket
+    __shared__ uint32_t cur[GB_MAX_P];               // output position of the bucket's next record
+    __shared__ uint32_t lo[GB_MAX_P];                // first position held in the bucket's line buffer
+    const int64_t n = eff_n(a.n_bound, a.n_dev);
+    const int64_t nch = (n + chunk_rows - 1) / chunk_rows;
+    const int64_t c0 = nch * blockIdx.x / gridDim.x, c1 = nch * (blockIdx.x + 1) / gridDim.x;
+    if (c0 >= c1) return;                            // same for the whole workgroup
+    const int64_t row0 = c0 * chunk_rows;
+    const int64_t row1 = c1 * chunk_rows < n ? c1 * chunk_rows : n;
+#pragma unroll
+    for (int i = 0; i < GPER; ++i) {
+        const int b = threadIdx.x + i * GL_THREADS;
+        if (b < P) {
+            const uint32_t g = gofs[c0 * P + b];
+            cur[b] = g;
+            lo[b] = g;
+            cnt[b] = 0;
+        }
+    }
+    auto load_ids = [&](int64_t base, int32_t *v, int32_t *k) {
+#pragma unroll
+        for (int c = 0; c < GL_ITEMS; ++c) {
+            const int64_t j = base + c * GL_THREADS + threadIdx.x;
+            v[c] = 0;
+            k[c] = 0;
+            if (j < row1) {
+                v[c] = a.rowid ? __builtin_nontemporal_load(&a.rowid[j]) : static_cast<int32_t>(j);
+                if (K32 && !a.key32_by_rowid) k[c] = __builtin_nontemporal_load(&a.key32[j]);
+            }
+        }
+    };
+    auto load_vals = [&](int64_t base, const int32_t *v, int32_t *k, int64_t *q, int64_t *p, int64_t *d,
+                         bool *keep) {
+#pragma unroll
+        for (int c = 0; c < GL_ITEMS; ++c) {
+            const int64_t j = base + c * GL_THREADS + threadIdx.x;
+            keep[c] = j < row1 && (!a.filter || row_pass(a, v[c]));
+            q[c] = p[c] = d[c] = 0;
+            if (keep[c]) {
+                if (K32 && a.key32_by_rowid) k[c] = a.key32[v[c]];
+                q[c] = __builtin_nontemporal_load(&a.qty[v[c]]);
+                p[c] = __builtin_nontemporal_load(&a.price[v[c]]);
+                d[c] = __builtin_nontemporal_load(&a.disc[v[c]]);
+            }
+        }
+    };
+    int32_t v0[GL_ITEMS], k0[GL_ITEMS], v1[GL_ITEMS], k1[GL_ITEMS];
+    int64_t q0[GL_ITEMS], p0[GL_ITEMS], d0[GL_ITEMS];
+    bool keep0[GL_ITEMS];
+    load_ids(row0, v0, k0);
+    load_vals(row0, v0, k0, q0, p0, d0, keep0);
+    load_ids(row0 + GL_TILE, v1, k1);
+    for (int64_t base = row0; base < row1; base += GL_TILE) {
+        int64_t q1[GL_ITEMS], p1[GL_ITEMS], d1[GL_ITEMS];
+        bool keep1[GL_ITEMS];
+        load_vals(base + GL_TILE, v1, k1, q1, p1, d1, keep1);      // the next tile's gathers
+        int32_t v2[GL_ITEMS], k2[GL_ITEMS];
+        load_ids(base + 2 * GL_TILE, v2, k2);                       // and the ids of the one after
+        gq_lds_barrier();                                           // the last tile's write-out is done
+#pragma unroll
+        for (int i = 0; i < GPER; ++i) {
+            const int b = threadIdx.x + i * GL_THREADS;
+            if (b < P) {
+                cur[b] += cnt[b];
+                cnt[b] = 0;
+            }
+        }
+        gq_lds_barrier();
+        uint4 rec[GL_ITEMS];
+        uint32_t bk[GL_ITEMS], rank[GL_ITEMS];
+#pragma unroll
+        for (int c = 0; c < GL_ITEMS; ++c) {
+            if (keep0[c]) {
+                const int64_t j = base + c * GL_THREADS + threadIdx.x;
+                const gq_i128 rev = gq_revenue(p0[c], a.rev_scale, d0[c]);
+                const bool nar = is_narrow(q0[c], rev);
+                if (!nar) side[atomicAdd(side_cnt, 1u)] = static_cast<uint32_t>(j);
+                const uint64_t r = nar ? rev.lo : 0ull;
+                rec[c] = make_uint4(static_cast<uint32_t>(k0[c]), nar ? static_cast<uint32_t>(q0[c]) : 0u,
+                                    static_cast<uint32_t>(r), static_cast<uint32_t>(r >> 32));
+                bk[c] = gb_bucket(gb_hash(0, k0[c]), P);
+                rank[c] = atomicAdd(&cnt[bk[c]], 1u);
+            }
+        }
+        gq_lds_barrier();
+        // a line that this tile completes: its older records leave the buffer
+#pragma unroll
+        for (int i = 0; i < GPER; ++i) {
+            const int b = threadIdx.x + i * GL_THREADS;
+            const uint32_t k = b < P ? cnt[b] : 0u;
+            if (k) {
+                const uint32_t g = cur[b];
+                const uint32_t cut = (g + k) & LMASK;
+                if ((g & LMASK) < cut) {
+                    for (uint32_t x = lo[b]; x < g; ++x) recs[x] = lbuf[b * GL_LINE + (x & (GL_LINE - 1))];
+                    lo[b] = cut;
+                }
+            }
+        }
+        gq_lds_barrier();                                           // the buffers are read
+        // the new records: complete lines to the output, the rest to the buffer
+#pragma unroll
+        for (int c = 0; c < GL_ITEMS; ++c) {
+            if (keep0[c]) {
+                const uint32_t b = bk[c];
+                const uint32_t g = cur[b];
+                const uint32_t x = g + rank[c];
+                const uint32_t cut = (g + cnt[b]) & LMASK;
+                if (x < cut) recs[x] = rec[c];
+                else lbuf[b * GL_LINE + (x & (GL_LINE - 1))] = rec[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < GL_ITEMS; ++c) {
+            k0[c] = k1[c];
+            q0[c] = q1[c];
+            p0[c] = p1[c];
+            d0[c] = d1[c];
+            keep0[c] = keep1[c];
+            v1[c] = v2[c];
+            k1[c] = k2[c];
+        }
+    }
+    gq_lds_barrier();
+    // the open end of every stretch
+#pragma unroll
+    for (int i = 0; i < GPER; ++i) {
+        const int b = threadIdx.x + i * GL_THREADS;
+        if (b < P) {
+            const uint32_t g = cur[b] + cnt[b];
+            for (uint32_t x = lo[b]; x < g; ++x) recs[x] = lbuf[b * GL_LINE + (x & (GL_LINE - 1))];
+        }
+    }
+}
+
 // Full values of the wide rows into the global table (count 0: their rows
 // were counted by their narrow records).
 template <bool K64, bool K32>
@@ -1223,9 +1387,11 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
     gb_plan pl{};
     pl.small = max_groups <= GB_SMALL_GROUPS;
     pl.gslots = next_pow2(static_cast<uint64_t>(max_groups > 32 ? 2 * max_groups : 64));
+    // hist chunks: one tile of the tile scatter (key64 records), or a chunk
+    // of the region scatter (16-byte records)
     const int64_t tile = static_cast<int64_t>(GB_THREADS) * 8;        // gb_fmt<>::TILE
-    pl.chunk_rows = tile;
-    pl.ntiles = n > 0 ? (n + tile - 1) / tile : 1;
+    pl.chunk_rows = (!pl.small && !k64) ? GL_CHUNK_ROWS : tile;
+    pl.ntiles = n > 0 ? (n + pl.chunk_rows - 1) / pl.chunk_rows : 1;
     pl.words = k64 ? 3 : 2;
     if (!pl.small) {
         // about 40% of a bucket's LDS table for the expected groups: the
@@ -1332,11 +1498,20 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
     // b mod 8 = x, so the grid is a whole number of rounds over the eight
     // XCDs (at least one workgroup each, even for fewer than 8 tiles); a
     // workgroup whose range is empty exits at once
-    int64_t sgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * (K64 ? 2 : 3));
-    sgrid = (sgrid + GQ_NUM_XCD - 1) / GQ_NUM_XCD * GQ_NUM_XCD;
-    GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(static_cast<uint32_t>(sgrid)),
-                     dim3(GB_THREADS), 0, s, a, P1, static_cast<const uint32_t *>(w.hist), recs1, w.side,
-                     w.side_cnt, w.side_cnt + 32));
+    if constexpr (K64) {
+        int64_t sgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus) * 2);
+        sgrid = (sgrid + GQ_NUM_XCD - 1) / GQ_NUM_XCD * GQ_NUM_XCD;
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_kernel<K64, K32>, dim3(static_cast<uint32_t>(sgrid)),
+                         dim3(GB_THREADS), 0, s, a, P1, static_cast<const uint32_t *>(w.hist), recs1, w.side,
+                         w.side_cnt, w.side_cnt + 32));
+    } else {
+        // one region per CU (a workgroup takes most of a CU's LDS)
+        const int64_t rgrid = std::min<int64_t>(grid, static_cast<int64_t>(ctx->num_cus));
+        GQ_TRY(gq_launch(ctx, "gq_groupby_scatter", gb_scatter_lines_kernel<K32>,
+                         dim3(static_cast<uint32_t>(rgrid)), dim3(GL_THREADS), 0, s, a, P1, pl.chunk_rows,
+                         static_cast<const uint32_t *>(w.hist), reinterpret_cast<uint4 *>(recs1), w.side,
+                         w.side_cnt));
+    }
     if (pl.wide) {                                      // level 2: each super-bucket by its sub-buckets
         GQ_TRY(gq_launch(ctx, "gq_groupby_tiles2", gb_tiles2_kernel, dim3(1), dim3(256), 0, s,
                          static_cast<const uint32_t *>(w.startA), GB_P1, w.tpre));

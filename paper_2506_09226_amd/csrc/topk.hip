@@ -8,13 +8,14 @@
 // Stage 1 (many workgroups, one pass over the data): each workgroup streams a
 // contiguous chunk of the selection; rows whose key beats the workgroup's
 // current threshold are appended to an LDS candidate buffer; when the buffer
-// could overflow it is bitonic-sorted, cut to the best k, and the k-th key
-// becomes the new threshold.  The workgroup's best k go to a candidate array,
-// best first.  Row ids are loaded two steps ahead and values one step ahead,
-// and the per-step barriers order LDS only, so the loads stay in flight.
-// Stage 2 merges the candidate lists with the same buffer loop: first groups
-// of lists in parallel (one workgroup per group, each keeping its best k),
-// then one workgroup over the group results, which writes the answer.
+// could overflow, a radix selection cuts it to the best k and raises the
+// threshold to (the leading digits of) the k-th key.  The workgroup's best k
+// go to a candidate array.  Row ids are loaded two steps ahead and values one
+// step ahead, and the per-step barriers order LDS only, so the loads stay in
+// flight.  Stage 2 merges the candidate lists with the same buffer loop:
+// first groups of lists in parallel (one workgroup per group, each keeping its
+// best k), then one workgroup over the group results, which sorts its best k
+// (bitonic) and writes the answer.
 #include "gq_device.h"
 #include "gq_internal.h"
 
@@ -44,6 +45,9 @@ struct tk_lds {
     uint64_t th_ok;
     uint32_t th_rk;
     uint32_t has_th;
+    uint32_t hist[2][256];          // digit counts of the selection, two passes in turn
+    uint32_t sel_bin, sel_need, sel_cnt;
+    uint32_t scan[TK_THREADS / 64];
 };
 
 // Bitonic sort, best first, of the first `size` (power of two) entries.
@@ -73,8 +77,8 @@ GQ_DEV void tk_sort(tk_lds &L, int size)
     }
 }
 
-// Sort the buffer, keep the best k, update the threshold.  Block-wide.
-GQ_DEV void tk_compact(tk_lds &L, int k)
+// Sort the first L.count entries, best first.  Block-wide.
+GQ_DEV void tk_sort_count(tk_lds &L)
 {
     const int cnt = static_cast<int>(L.count);
     int size = 64;
@@ -85,13 +89,112 @@ GQ_DEV void tk_compact(tk_lds &L, int k)
     }
     gq_lds_barrier();
     tk_sort(L, size);
-    if (threadIdx.x == 0) {
-        if (cnt >= k) {
-            L.count = static_cast<uint32_t>(k);
-            L.th_ok = L.ok[k - 1];
-            L.th_rk = L.rk[k - 1];
-            L.has_th = 1;
+}
+
+// Keep the best k entries of the buffer (in no particular order) and raise
+// the threshold, by radix selection over the 96-bit keys (ok, then rk),
+// eight bits at a time from the top.  A pass counts, among the entries that
+// carry the digits chosen so far, how many take each value of the next digit;
+// the chosen value is the one at which the count of better entries reaches
+// the number still needed.  Once every entry carrying the chosen digits is
+// needed, those entries and all better ones are exactly the best k.  The new
+// threshold is the chosen digits followed by zero bits: no larger than the
+// k-th best key, so no key that belongs in the best k is turned away later.
+// Keys are unique (the row part differs), so the selection always ends.
+// Block-wide; L.count must be the same in every thread on entry.
+constexpr int TK_PER = TK_CAP / TK_THREADS;           // buffer entries per thread
+
+GQ_DEV void tk_select(tk_lds &L, int k)
+{
+    const uint32_t cnt = L.count;
+    if (cnt <= static_cast<uint32_t>(k)) return;
+    uint64_t ok[TK_PER];
+    uint32_t rk[TK_PER];
+    uint32_t valid = 0;
+#pragma unroll
+    for (int i = 0; i < TK_PER; ++i) {
+        const uint32_t e = threadIdx.x + i * TK_THREADS;
+        const bool v = e < cnt;
+        ok[i] = v ? L.ok[e] : 0;
+        rk[i] = v ? L.rk[e] : 0;
+        valid |= v ? (1u << i) : 0u;
+    }
+    for (int i = threadIdx.x; i < 256; i += TK_THREADS) L.hist[0][i] = 0;
+    gq_lds_barrier();
+    uint64_t p_ok = 0, m_ok = 0;                      // chosen digits and their mask
+    uint32_t p_rk = 0, m_rk = 0;
+    uint32_t need = static_cast<uint32_t>(k);
+    for (int d = 0; d < 12; ++d) {
+        uint32_t *h = L.hist[d & 1];
+        const int sh = d < 8 ? 56 - 8 * d : 24 - 8 * (d - 8);
+#pragma unroll
+        for (int i = 0; i < TK_PER; ++i) {
+            if (((valid >> i) & 1u) && (ok[i] & m_ok) == p_ok && (rk[i] & m_rk) == p_rk) {
+                const uint32_t dig = d < 8 ? static_cast<uint32_t>(ok[i] >> sh) & 255u : (rk[i] >> sh) & 255u;
+                atomicAdd(&h[dig], 1u);
+            }
         }
+        for (int i = threadIdx.x; i < 256; i += TK_THREADS) L.hist[(d + 1) & 1][i] = 0;
+        gq_lds_barrier();
+        if (threadIdx.x < 64) {                       // one wave finds the digit, from 255 down
+            const uint32_t lane = threadIdx.x;
+            uint32_t hb[4], sum = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                hb[j] = h[255 - 4 * lane - j];
+                sum += hb[j];
+            }
+            const uint32_t incl = gq_wave_inclusive_scan(sum);
+            uint32_t acc = incl - sum;
+            if (acc < need && need <= incl) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (acc < need && need <= acc + hb[j]) {
+                        L.sel_bin = 255 - 4 * lane - j;
+                        L.sel_need = need - acc;
+                        L.sel_cnt = hb[j];
+                    }
+                    acc += hb[j];
+                }
+            }
+        }
+        gq_lds_barrier();
+        const uint32_t bin = L.sel_bin, c = L.sel_cnt;
+        need = L.sel_need;
+        if (d < 8) {
+            p_ok |= static_cast<uint64_t>(bin) << sh;
+            m_ok |= 255ull << sh;
+        } else {
+            p_rk |= bin << sh;
+            m_rk |= 255u << sh;
+        }
+        if (c == need) break;                         // same in every thread
+    }
+    // the kept entries: chosen digits at least the prefix
+    bool kp[TK_PER];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int i = 0; i < TK_PER; ++i) {
+        const uint64_t a = ok[i] & m_ok;
+        const uint32_t b = rk[i] & m_rk;
+        kp[i] = ((valid >> i) & 1u) && (a > p_ok || (a == p_ok && b >= p_rk));
+        keep += kp[i] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t pos = gq_block_exclusive_scan_lds<TK_THREADS>(keep, &total, L.scan);
+#pragma unroll
+    for (int i = 0; i < TK_PER; ++i) {
+        if (kp[i]) {
+            L.ok[pos] = ok[i];
+            L.rk[pos] = rk[i];
+            ++pos;
+        }
+    }
+    if (threadIdx.x == 0) {
+        L.count = total;                              // k
+        L.th_ok = p_ok;
+        L.th_rk = p_rk;
+        L.has_th = 1;
     }
     gq_lds_barrier();
 }
@@ -177,7 +280,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
         gq_lds_barrier();
         const uint32_t cnt_now = L.count;      // same value in every thread
         gq_lds_barrier();
-        if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_compact(L, k);
+        if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_select(L, k);
 #pragma unroll
         for (int c = 0; c < TK_STEP_ITEMS; ++c) {
             r0[c] = r1[c];
@@ -185,7 +288,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
             r1[c] = r2[c];
         }
     }
-    tk_compact(L, k);
+    tk_select(L, k);
     const uint32_t cnt = L.count < static_cast<uint32_t>(k) ? L.count : static_cast<uint32_t>(k);
     for (uint32_t i = threadIdx.x; i < cnt; i += TK_THREADS) {
         cand_ok[static_cast<int64_t>(blockIdx.x) * k + i] = L.ok[i];
@@ -194,8 +297,9 @@ __global__ __launch_bounds__(TK_THREADS) void topk_stage1_kernel(const int64_t *
     if (threadIdx.x == 0) cand_cnt[blockIdx.x] = cnt;
 }
 
-// Merge lists [blockIdx.x * per, +per) of up to k keys each (best first)
-// into the best k; the last level (out_ok == nullptr) writes the answer.
+// Merge lists [blockIdx.x * per, +per) of up to k keys each (in any order)
+// into the best k; the last level (out_ok == nullptr) sorts them and writes
+// the answer.
 __global__ __launch_bounds__(TK_THREADS) void topk_merge_kernel(const uint64_t *__restrict__ in_ok,
                                                                 const uint32_t *__restrict__ in_rk,
                                                                 const uint32_t *__restrict__ in_cnt, int nlists,
@@ -242,9 +346,9 @@ __global__ __launch_bounds__(TK_THREADS) void topk_merge_kernel(const uint64_t *
         gq_lds_barrier();
         const uint32_t cnt_now = L.count;      // same value in every thread
         gq_lds_barrier();
-        if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_compact(L, k);
+        if (cnt_now > static_cast<uint32_t>(TK_CAP - TK_STEP)) tk_select(L, k);
     }
-    tk_compact(L, k);
+    tk_select(L, k);
     const uint32_t cnt = L.count < static_cast<uint32_t>(k) ? L.count : static_cast<uint32_t>(k);
     if (out_ok) {
         for (uint32_t x = threadIdx.x; x < cnt; x += TK_THREADS) {
@@ -254,6 +358,7 @@ __global__ __launch_bounds__(TK_THREADS) void topk_merge_kernel(const uint64_t *
         if (threadIdx.x == 0) out_cnt[blockIdx.x] = cnt;
         return;
     }
+    tk_sort_count(L);                                   // the answer, best first
     for (uint32_t x = threadIdx.x; x < cnt; x += TK_THREADS) {
         const uint64_t o = L.ok[x];
         const uint64_t u = desc ? o : ~o;
