@@ -1173,15 +1173,18 @@ GQ_DEV void lds_add_sums(lds_table<SLOTS, K64, K32> &T, int s, uint32_t cnt, uin
 // Chunks of the bucket pass.  A bucket of at most chunk_rows rows is one
 // chunk; a larger one (a bucket holding a heavy key) is cut into
 // ceil(rows / chunk_rows) chunks, each aggregated by its own workgroup.
-// cstart[b] = number of chunks before bucket b (one workgroup of
-// GB_BUCKET_THREADS threads; P <= GB_MAX_P_WIDE).
+// cstart[b] = number of chunks before bucket b.  order[] lists the chunks in
+// the order the bucket pass takes them: the chunks of split buckets first
+// (the longest work, so none of it is left for the end), then the buckets of
+// one chunk.  One workgroup of GB_BUCKET_THREADS threads; P <= GB_MAX_P_WIDE.
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint32_t *__restrict__ start, int P,
-                                                                      int64_t chunk_rows, uint32_t *__restrict__ cstart)
+                                                                      int64_t chunk_rows, uint32_t *__restrict__ cstart,
+                                                                      uint32_t *__restrict__ order)
 {
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     constexpr int PER = GB_MAX_P_WIDE / GB_BUCKET_THREADS;
     uint32_t nch[PER];
-    uint32_t mine = 0;
+    uint32_t mine = 0, msplit = 0, mone = 0;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = threadIdx.x * PER + i;
@@ -1191,161 +1194,208 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint
             nch[i] = rows > chunk_rows ? static_cast<uint32_t>((rows + chunk_rows - 1) / chunk_rows) : 1u;
         }
         mine += nch[i];
+        msplit += nch[i] > 1 ? nch[i] : 0u;
+        mone += nch[i] == 1 ? 1u : 0u;
     }
-    uint32_t total;
+    uint32_t total, nsplit, none;
     uint32_t run = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &total, scan_smem);
+    uint32_t srun = gq_block_exclusive_scan<GB_BUCKET_THREADS>(msplit, &nsplit, scan_smem);
+    uint32_t orun = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mone, &none, scan_smem);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = threadIdx.x * PER + i;
-        if (b < P) cstart[b] = run;
+        if (b < P) {
+            cstart[b] = run;
+            if (nch[i] > 1) {
+                for (uint32_t j = 0; j < nch[i]; ++j) order[srun + j] = run + j;
+                srun += nch[i];
+            } else if (nch[i] == 1) {
+                order[nsplit + orun] = run;
+                ++orun;
+            }
+        }
         run += nch[i];
     }
     if (threadIdx.x == 0) cstart[P] = total;
 }
 
-// One workgroup per chunk (grid: an upper bound on the chunk count; the
-// surplus workgroups exit).  A workgroup aggregates its rows in an LDS table.
-// A bucket that is one chunk writes its groups out directly; each chunk of a
-// split bucket adds its partial groups to the global table instead (a few
-// device atomics per group and chunk), which the table's emit pass writes out.
-// Lanes of a wave that update the same slot are summed across the wave first
-// and added by one lane, so a heavy key costs one LDS update per wave rather
-// than one per row.
+// Persistent: one workgroup per CU takes chunks from a queue (order[], via a
+// counter) until none is left, and aggregates each chunk's rows in an LDS
+// table.  A bucket that is one chunk writes its groups out directly; each
+// chunk of a split bucket adds its partial groups to the global table
+// instead (a few device atomics per group and chunk), which the table's emit
+// pass writes out.  The next chunk is taken when a chunk starts, and its
+// first records are loaded during the current chunk's last step, so they
+// arrive while the current chunk writes its groups.  Lanes of a wave that
+// update the same slot are summed across the wave first and added by one
+// lane, so a heavy key costs one LDS update per wave rather than one per row.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint64_t *__restrict__ recs,
                                                                       const uint32_t *__restrict__ start,
-                                                                      const uint32_t *__restrict__ cstart, int P,
+                                                                      const uint32_t *__restrict__ cstart,
+                                                                      const uint32_t *__restrict__ order, int P,
                                                                       int64_t chunk_rows, const uint32_t *side_cnt,
-                                                                      gtable g, gq_groups out, uint32_t *status)
+                                                                      uint32_t *qctr, gtable g, gq_groups out,
+                                                                      uint32_t *status)
 {
     constexpr int SLOTS = bucket_slots<K64, K32>::value;
     __shared__ lds_table<SLOTS, K64, K32> T;
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     __shared__ unsigned long long s_base;
-    const uint32_t ch = blockIdx.x;
-    if (ch >= cstart[P]) return;                     // same value for the whole workgroup
-    int b = 0;                                       // the bucket of chunk ch: last b with cstart[b] <= ch
-    for (int hi = P - 1; b < hi;) {
-        const int mid = (b + hi + 1) >> 1;
-        if (cstart[mid] <= ch) b = mid;
-        else hi = mid - 1;
-    }
-    const uint32_t nch = cstart[b + 1] - cstart[b];
-    const bool split = nch > 1;
-    const int64_t b0 = start[b], b1 = start[b + 1];
-    const int64_t r0 = split ? b0 + static_cast<int64_t>(ch - cstart[b]) * chunk_rows : b0;
-    const int64_t r1 = split ? (r0 + chunk_rows < b1 ? r0 + chunk_rows : b1) : b1;
-    lds_init(T);
-    __syncthreads();
+    __shared__ uint32_t s_item;
+    const uint32_t total = cstart[P];
+    // rows [r0, r1) of queue item `item`, and whether its bucket is split
+    auto geom = [&](uint32_t item, int64_t &r0, int64_t &r1, bool &split) {
+        const uint32_t ch = order[item];
+        int b = 0;                                   // the bucket of chunk ch: last b with cstart[b] <= ch
+        for (int hi = P - 1; b < hi;) {
+            const int mid = (b + hi + 1) >> 1;
+            if (cstart[mid] <= ch) b = mid;
+            else hi = mid - 1;
+        }
+        split = cstart[b + 1] - cstart[b] > 1;
+        const int64_t b0 = start[b], b1 = start[b + 1];
+        r0 = split ? b0 + static_cast<int64_t>(ch - cstart[b]) * chunk_rows : b0;
+        r1 = split ? (r0 + chunk_rows < b1 ? r0 + chunk_rows : b1) : b1;
+    };
     constexpr int STEP = GB_BUCKET_THREADS * GB_BUCKET_ITEMS;
     // the records of the next step are loaded while this step's are aggregated
     int64_t nk64[GB_BUCKET_ITEMS], nq[GB_BUCKET_ITEMS], nrv[GB_BUCKET_ITEMS];
     int32_t nk32[GB_BUCKET_ITEMS];
-    auto load_step = [&](int64_t i0) {
+    auto load_step = [&](int64_t i0, int64_t end) {
 #pragma unroll
         for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
             const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
             nk64[c] = nq[c] = nrv[c] = 0;
             nk32[c] = 0;
-            if (i < r1) read_words<K64, K32>(recs, i, nk64[c], nk32[c], nq[c], nrv[c]);
+            if (i < end) read_words<K64, K32>(recs, i, nk64[c], nk32[c], nq[c], nrv[c]);
         }
     };
-    load_step(r0);
-    for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
-        int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
-        int32_t k32[GB_BUCKET_ITEMS];
+    if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
+    __syncthreads();
+    uint32_t item = s_item;
+    if (item >= total) return;                       // same for the whole workgroup
+    int64_t r0, r1;
+    bool split;
+    geom(item, r0, r1, split);
+    bool have = false;                               // n*[] hold the first step of this item
+    const bool merge = *side_cnt != 0u;              // same value for every thread
+    while (true) {
+        if (!have) load_step(r0, r1);
+        lds_init(T);
+        __syncthreads();                             // the table is clear; every thread has read s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
+        __syncthreads();
+        const uint32_t nitem = s_item;
+        int64_t nr0 = 0, nr1 = 0;
+        bool nsplit = false;
+        if (nitem < total) geom(nitem, nr0, nr1, nsplit);
+        bool have_next = false;
+        for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
+            int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
+            int32_t k32[GB_BUCKET_ITEMS];
 #pragma unroll
-        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
-            k64[c] = nk64[c];
-            k32[c] = nk32[c];
-            q[c] = nq[c];
-            rv[c] = nrv[c];
+            for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+                k64[c] = nk64[c];
+                k32[c] = nk32[c];
+                q[c] = nq[c];
+                rv[c] = nrv[c];
+            }
+            if (i0 + STEP < r1) {
+                load_step(i0 + STEP, r1);
+            } else if (nitem < total) {              // the next item's first step
+                load_step(nr0, nr1);
+                have_next = true;
+            }
+#pragma unroll
+            for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+                const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
+                const bool active = i < r1;
+                gq_i128 rev;
+                rev.lo = static_cast<uint64_t>(rv[c]);
+                rev.hi = rv[c] >> 63;
+                const uint64_t h = gb_hash(k64[c], k32[c]);
+                const int s = lds_find(T, active, h, k64[c], k32[c]);
+                bool mine = active && s >= 0;
+                const uint64_t am = gq_ballot(mine);
+                if (am) {
+                    // the slot of the first updating lane, summed over every lane that updates it
+                    const int lead = __builtin_ctzll(am);
+                    const int sl = __builtin_amdgcn_readlane(s, lead);
+                    const bool in = mine && s == sl;
+                    const uint64_t same = gq_ballot(in);
+                    if (__popcll(same) > 1) {
+                        const uint32_t cn = gq_wave_sum<uint32_t>(in ? 1u : 0u);
+                        const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
+                        const uint64_t lo = gq_wave_sum<uint64_t>(
+                            in ? static_cast<uint64_t>(static_cast<uint32_t>(static_cast<uint64_t>(rv[c]))) : 0ull);
+                        const int64_t hs = gq_wave_sum<int64_t>(in ? (rv[c] >> 32) : 0);
+                        if (gq_lane() == lead) lds_add_sums(T, sl, cn, sq, lo, hs);
+                        mine = mine && !in;
+                    }
+                }
+                if (mine) lds_add_split(T, s, q[c], rv[c]);
+                const bool spill = active && s < 0;
+                const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
+                if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
+            }
         }
-        load_step(i0 + STEP);
+        __syncthreads();
+        if (split) {
+            for (int s = threadIdx.x; s < SLOTS; s += GB_BUCKET_THREADS) {
+                const bool occ = lds_occupied(T, s);
+                const int64_t k64 = occ ? lds_key64(T, s) : 0;
+                const int32_t k32 = occ ? lds_key32(T, s) : 0;
+                const int64_t gs = g_find<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32, status);
+                if (occ && gs >= 0) g_add(g, gs, T.cnt[s], T.sq[s], lds_split_total(T.lo[s], T.hi[s]));
+            }
+        } else {
+            // emit: each thread owns SLOTS / GB_BUCKET_THREADS consecutive slots
+            constexpr int PER = SLOTS / GB_BUCKET_THREADS;
+            uint32_t mine = 0;
 #pragma unroll
-        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
-            const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
-            const bool active = i < r1;
-            gq_i128 rev;
-            rev.lo = static_cast<uint64_t>(rv[c]);
-            rev.hi = rv[c] >> 63;
-            const uint64_t h = gb_hash(k64[c], k32[c]);
-            const int s = lds_find(T, active, h, k64[c], k32[c]);
-            bool mine = active && s >= 0;
-            const uint64_t am = gq_ballot(mine);
-            if (am) {
-                // the slot of the first updating lane, summed over every lane that updates it
-                const int lead = __builtin_ctzll(am);
-                const int sl = __builtin_amdgcn_readlane(s, lead);
-                const bool in = mine && s == sl;
-                const uint64_t same = gq_ballot(in);
-                if (__popcll(same) > 1) {
-                    const uint32_t cn = gq_wave_sum<uint32_t>(in ? 1u : 0u);
-                    const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
-                    const uint64_t lo = gq_wave_sum<uint64_t>(
-                        in ? static_cast<uint64_t>(static_cast<uint32_t>(static_cast<uint64_t>(rv[c]))) : 0ull);
-                    const int64_t hs = gq_wave_sum<int64_t>(in ? (rv[c] >> 32) : 0);
-                    if (gq_lane() == lead) lds_add_sums(T, sl, cn, sq, lo, hs);
-                    mine = mine && !in;
+            for (int i = 0; i < PER; ++i) mine += lds_occupied(T, threadIdx.x * PER + i) ? 1u : 0u;
+            uint32_t all;
+            uint32_t pre = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &all, scan_smem);
+            if (threadIdx.x == 0)
+                s_base = all ? atomicAdd(reinterpret_cast<unsigned long long *>(out.n_groups),
+                                         static_cast<unsigned long long>(all))
+                             : 0ull;
+            __syncthreads();
+            int64_t idx = static_cast<int64_t>(s_base) + pre;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int s = threadIdx.x * PER + i;
+                const bool occ = lds_occupied(T, s);
+                const int64_t k64 = occ ? lds_key64(T, s) : 0;
+                const int32_t k32 = occ ? lds_key32(T, s) : 0;
+                uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0;
+                const gq_i128 tot = lds_split_total(occ ? T.lo[s] : 0, occ ? T.hi[s] : 0);
+                uint64_t lo = tot.lo;
+                int64_t hi = tot.hi;
+                if (merge) {
+                    const int64_t gs = g_lookup<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32);
+                    if (occ && gs >= 0) {
+                        cnt += g.cnt[gs];
+                        sq += g.sq[gs];
+                        const uint64_t l2 = lo + g.lo[gs];
+                        hi += g.hi[gs] + (l2 < lo ? 1 : 0);
+                        lo = l2;
+                        __hip_atomic_store(&g.state[gs], 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                if (occ) {
+                    emit_group(out, idx, k64, k32, cnt, sq, lo, hi, status);
+                    ++idx;
                 }
             }
-            if (mine) lds_add_split(T, s, q[c], rv[c]);
-            const bool spill = active && s < 0;
-            const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
-            if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
         }
-    }
-    if (split) {
-        __syncthreads();
-        for (int s = threadIdx.x; s < SLOTS; s += GB_BUCKET_THREADS) {
-            const bool occ = lds_occupied(T, s);
-            const int64_t k64 = occ ? lds_key64(T, s) : 0;
-            const int32_t k32 = occ ? lds_key32(T, s) : 0;
-            const int64_t gs = g_find<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32, status);
-            if (occ && gs >= 0) g_add(g, gs, T.cnt[s], T.sq[s], lds_split_total(T.lo[s], T.hi[s]));
-        }
-        return;
-    }
-    __syncthreads();
-    // emit: each thread owns SLOTS / GB_BUCKET_THREADS consecutive slots
-    constexpr int PER = SLOTS / GB_BUCKET_THREADS;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) mine += lds_occupied(T, threadIdx.x * PER + i) ? 1u : 0u;
-    uint32_t total;
-    uint32_t pre = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &total, scan_smem);
-    if (threadIdx.x == 0)
-        s_base = total ? atomicAdd(reinterpret_cast<unsigned long long *>(out.n_groups),
-                                   static_cast<unsigned long long>(total))
-                       : 0ull;
-    __syncthreads();
-    const bool merge = *side_cnt != 0u;            // same value for every thread
-    int64_t idx = static_cast<int64_t>(s_base) + pre;
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int s = threadIdx.x * PER + i;
-        const bool occ = lds_occupied(T, s);
-        const int64_t k64 = occ ? lds_key64(T, s) : 0;
-        const int32_t k32 = occ ? lds_key32(T, s) : 0;
-        uint64_t cnt = occ ? T.cnt[s] : 0, sq = occ ? T.sq[s] : 0;
-        const gq_i128 tot = lds_split_total(occ ? T.lo[s] : 0, occ ? T.hi[s] : 0);
-        uint64_t lo = tot.lo;
-        int64_t hi = tot.hi;
-        if (merge) {
-            const int64_t gs = g_lookup<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32);
-            if (occ && gs >= 0) {
-                cnt += g.cnt[gs];
-                sq += g.sq[gs];
-                const uint64_t l2 = lo + g.lo[gs];
-                hi += g.hi[gs] + (l2 < lo ? 1 : 0);
-                lo = l2;
-                __hip_atomic_store(&g.state[gs], 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        if (occ) {
-            emit_group(out, idx, k64, k32, cnt, sq, lo, hi, status);
-            ++idx;
-        }
+        if (nitem >= total) break;                   // same for the whole workgroup
+        r0 = nr0;
+        r1 = nr1;
+        split = nsplit;
+        have = have_next;
+        __syncthreads();                             // the table is read out before it is cleared
     }
 }
 
@@ -1425,6 +1475,7 @@ struct gb_ws {
     uint32_t *hist;
     uint32_t *start;
     uint32_t *cstart;       // chunks of the bucket pass before each bucket
+    uint32_t *order;        // the bucket pass's chunk queue
     void *scan_ws;
     uint64_t *recs;         // partitioned rows, narrow records
     uint32_t *side;         // row indices of wide rows
@@ -1440,9 +1491,10 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     gb_ws w{};
     const size_t S = pl.gslots;
     w.g.state = c.take<uint32_t>(S);
-    // [0] wide rows; [32 (x + 1)] the scatter's tile counter of XCD x, one
-    // 128-byte line each
-    w.side_cnt = c.take<uint32_t>(32 * (GQ_NUM_XCD + 1));
+    // [0] wide rows; [32 (x + 1)] the scatter's tile counter of XCD x;
+    // [32 (GQ_NUM_XCD + 1)] the bucket pass's queue counter; one 128-byte
+    // line each
+    w.side_cnt = c.take<uint32_t>(32 * (GQ_NUM_XCD + 2));
     w.zero_bytes = c.off;                   // the state words and counters start at zero
     w.g.k64 = c.take<int64_t>(k64 ? S : 1);
     w.g.k32 = c.take<int32_t>(k32 ? S : 1);
@@ -1457,6 +1509,7 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
         w.hist = c.take<uint32_t>(static_cast<size_t>(pl.ntiles) * static_cast<size_t>(P1));
         w.start = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
         w.cstart = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
+        w.order = c.take<uint32_t>(static_cast<size_t>(pl.bucket_grid));
         w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, P1));
         w.recs = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
         w.side = c.take<uint32_t>(rows);
@@ -1531,11 +1584,16 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));
     GQ_TRY(gq_launch(ctx, "gq_groupby_chunks", gb_chunks_kernel, dim3(1), dim3(GB_BUCKET_THREADS), 0, s,
-                     static_cast<const uint32_t *>(w.start), pl.P, pl.bucket_chunk, w.cstart));
-    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(pl.bucket_grid)),
+                     static_cast<const uint32_t *>(w.start), pl.P, pl.bucket_chunk, w.cstart, w.order));
+    // one workgroup per CU (its LDS table takes most of a CU), each taking
+    // chunks from the queue
+    const int64_t bgrid = std::min<int64_t>(pl.bucket_grid, static_cast<int64_t>(ctx->num_cus));
+    GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(bgrid)),
                      dim3(GB_BUCKET_THREADS), 0, s, static_cast<const uint64_t *>(w.recs),
-                     static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.cstart), pl.P,
-                     pl.bucket_chunk, static_cast<const uint32_t *>(w.side_cnt), w.g, out, ctx->status_dev));
+                     static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.cstart),
+                     static_cast<const uint32_t *>(w.order), pl.P, pl.bucket_chunk,
+                     static_cast<const uint32_t *>(w.side_cnt), w.side_cnt + 32 * (GQ_NUM_XCD + 1), w.g, out,
+                     ctx->status_dev));
     return gq_launch(ctx, "gq_groupby_emit", gb_table_emit_kernel<K64, K32>, dim3(emit_blocks), dim3(256), 0, s, w.g,
                      out, ctx->status_dev);
 }
