@@ -374,6 +374,28 @@ def test_groupby_key64_direct_no_rowid(ctx, max_groups):
     _check_groups(res, exp, True, False)
 
 
+@pytest.mark.parametrize("max_groups", [64, 100_000])
+@pytest.mark.parametrize("composite", [False, True])
+def test_groupby_extreme_keys(ctx, max_groups, composite):
+    """Keys at the extremes of int64 and int32 (INT64_MIN, INT32_MIN among
+    them) beside ordinary keys, on the small and the large path, key64 alone
+    and composite: every group exact."""
+    n = 120_000
+    r = rng(23)
+    k64s = np.array([-(1 << 63), (1 << 63) - 1, -1, 0, 1, 123_456_789_012], dtype=np.int64)
+    k32s = np.array([-(1 << 31), (1 << 31) - 1, -1, 0, 7], dtype=np.int32)
+    key64 = k64s[r.integers(0, len(k64s), size=n)]
+    key32 = k32s[r.integers(0, len(k32s), size=n)] if composite else None
+    qty = r.integers(1, 51, size=n).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=n).astype(np.int64)
+    disc = r.integers(0, 11, size=n).astype(np.int64)
+    exp = oracle.groupby(n, qty, price, disc, key64=key64, key32=key32)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), key64=dev(key64),
+                            key32=dev(key32) if composite else None, max_groups=max_groups)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, True, composite)
+
+
 @pytest.mark.parametrize("groups", [25, 5000])
 def test_groupby_row_filter(ctx, groups):
     """Only rows whose value row passes filter_lo <= filter[v] < filter_hi."""
