@@ -101,17 +101,22 @@ GQ_DEV gb_row<K64, K32> load_row(const gb_args &a, int64_t j)
 }
 
 // ----------------------------------------------------------------- LDS table
-// Tables keyed by key64 use a state word (0 empty, 1 claiming, 2 published)
-// beside the key columns.  All other tables hold one 64-bit word per slot,
-// 0 = empty, else (key32 << 32) | 1, claimed and published by a single
-// compare-and-swap: one LDS access per probe and no claiming state to wait on.
+// Every table has one 64-bit key word per slot, claimed by a single
+// compare-and-swap.  Without key64 it is (key32 << 32) | 1 (0 = empty), so a
+// claim publishes the whole key at once.  With key64 it is the key64 itself
+// (LDS_EMPTY64 = empty); a composite key's key32 sits in a second word
+// (LDS_EMPTY32 until the claiming lane writes it), so a slot whose key64
+// matches and whose key32 is still empty is being claimed, and a lookup reads
+// it again.  A row whose key part equals an empty marker never enters an LDS
+// table: it goes to the global table, which has its own claiming state.
+constexpr uint64_t LDS_EMPTY64 = 0x8000000000000000ull;
+constexpr uint32_t LDS_EMPTY32 = 0x80000000u;
+
 template <int SLOTS, bool K64, bool K32>
 struct lds_table {
-    uint32_t state[K64 ? SLOTS : 1];
-    uint64_t word[K64 ? 1 : SLOTS];
-    uint32_t cnt[SLOTS];
+    uint64_t word[SLOTS];
     int32_t k32[(K64 && K32) ? SLOTS : 1];
-    int64_t k64[K64 ? SLOTS : 1];
+    uint32_t cnt[SLOTS];
     uint64_t sq[SLOTS];
     uint64_t lo[SLOTS];
     int64_t hi[SLOTS];
@@ -120,7 +125,7 @@ struct lds_table {
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV bool lds_occupied(const lds_table<SLOTS, K64, K32> &T, int s)
 {
-    if constexpr (K64) return T.state[s] == 2u;
+    if constexpr (K64) return T.word[s] != LDS_EMPTY64;
     else return T.word[s] != 0ull;
 }
 
@@ -134,7 +139,7 @@ GQ_DEV int32_t lds_key32(const lds_table<SLOTS, K64, K32> &T, int s)
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV int64_t lds_key64(const lds_table<SLOTS, K64, K32> &T, int s)
 {
-    if constexpr (K64) return T.k64[s];
+    if constexpr (K64) return static_cast<int64_t>(T.word[s]);
     else return 0;
 }
 
@@ -149,8 +154,8 @@ template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_init(lds_table<SLOTS, K64, K32> &T)
 {
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
-        if constexpr (K64) T.state[s] = 0;
-        else T.word[s] = 0;
+        T.word[s] = K64 ? LDS_EMPTY64 : 0ull;
+        if constexpr (K64 && K32) T.k32[s] = static_cast<int32_t>(LDS_EMPTY32);
         T.cnt[s] = 0;
         T.sq[s] = 0;
         T.lo[s] = 0;
@@ -208,25 +213,37 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
         }
     } else {
         // The same groups of four slots for tables keyed by key64: the four
-        // state words are read first; the keys of the published slots are
-        // compared; a slot being claimed (state 1) may be getting this very
-        // key, so the group is read again until it is published; with no
-        // match and no claim in progress the first empty slot is claimed.
+        // key64 words (and key32 words) of a group are read together; a slot
+        // with this key64 and an empty key32 is being claimed, so the group
+        // is read again; with no match and no claim in progress the first
+        // empty slot is claimed with one compare-and-swap of its key64 word,
+        // and the claiming lane then writes the key32 word.
+        if (K64 && (static_cast<uint64_t>(k64) == LDS_EMPTY64 ||
+                    (K32 && static_cast<uint32_t>(k32) == LDS_EMPTY32)))
+            done = true;                             // a marker value: the global table takes the row
         uint32_t g = s >> 2;
         while (__any(!done)) {
             if (!done) {
-                uint32_t st[4];
+                unsigned long long *gp = reinterpret_cast<unsigned long long *>(&T.word[4 * g]);
+                unsigned long long w[4];
+                uint32_t x[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = __hip_atomic_load(gp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    st[i] = __hip_atomic_load(&T.state[4 * g + i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    x[i] = K32 ? __hip_atomic_load(reinterpret_cast<uint32_t *>(&T.k32[4 * g + i]), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)
+                               : 0u;
+                const unsigned long long want = static_cast<unsigned long long>(k64);
                 int hit = -1, empty = -1;
                 bool claiming = false;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
-                    const int sl = static_cast<int>(4 * g) + i;
-                    if (st[i] == 2u && T.k64[sl] == k64 && (!K32 || T.k32[sl] == k32)) hit = i;
-                    if (st[i] == 0u) empty = i;
-                    claiming = claiming || st[i] == 1u;
+                    if (w[i] == want) {
+                        if (!K32 || x[i] == static_cast<uint32_t>(k32)) hit = i;
+                        else if (x[i] == LDS_EMPTY32) claiming = true;
+                    }
+                    if (w[i] == LDS_EMPTY64) empty = i;
                 }
                 if (hit >= 0) {
                     found = static_cast<int>(4 * g) + hit;
@@ -235,11 +252,10 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
                     // read the group again on the next pass
                 } else if (empty >= 0) {
                     const int sl = static_cast<int>(4 * g) + empty;
-                    if (atomicCAS(&T.state[sl], 0u, 1u) == 0u) {
-                        T.k64[sl] = k64;
-                        if (K32) T.k32[sl] = k32;
-                        __threadfence_block();
-                        atomicExch(&T.state[sl], 2u);
+                    if (atomicCAS(gp + empty, static_cast<unsigned long long>(LDS_EMPTY64), want) == LDS_EMPTY64) {
+                        if (K32)
+                            __hip_atomic_store(reinterpret_cast<uint32_t *>(&T.k32[sl]), static_cast<uint32_t>(k32),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         found = sl;
                         done = true;
                     }                                         // else: taken meanwhile; read again
@@ -301,6 +317,7 @@ struct gtable {
     uint64_t *lo;
     int64_t *hi;
     uint64_t mask;
+    uint32_t *used;         // groups claimed so far (0: the table's emit has nothing to write)
 };
 
 template <bool K64, bool K32>
@@ -322,6 +339,7 @@ GQ_DEV int64_t g_find(const gtable &g, bool active, uint64_t h, int64_t k64, int
                 __hip_atomic_store(&g.lo[s], uint64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&g.hi[s], int64_t{0}, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&g.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                atomicAdd(g.used, 1u);
                 found = static_cast<int64_t>(s);
                 done = true;
             } else if (st >= 2u) {                      // published (2) or taken (3)
@@ -480,6 +498,7 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 {
     __shared__ uint32_t scan_smem[256 / 64];
     __shared__ unsigned long long s_base;
+    if (*g.used == 0u) return;                       // nothing was claimed: no slot to scan
     const uint64_t slots = g.mask + 1;
     const uint64_t per = (slots + gridDim.x - 1) / gridDim.x;
     const uint64_t s0 = static_cast<uint64_t>(blockIdx.x) * per;
@@ -1159,6 +1178,16 @@ struct bucket_slots {
     static constexpr int value = K64 ? 3072 : 4096;
 };
 
+// A partial group of one chunk of a split bucket (exact int128 revenue).
+struct gb_part {
+    int64_t k64;
+    int32_t k32;
+    uint32_t cnt;
+    uint64_t sq;
+    uint64_t lo;
+    int64_t hi;
+};
+
 // Sums of several rows into slot s (the split form of lds_add_split).
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_add_sums(lds_table<SLOTS, K64, K32> &T, int s, uint32_t cnt, uint64_t qty, uint64_t lo_sum,
@@ -1179,7 +1208,8 @@ GQ_DEV void lds_add_sums(lds_table<SLOTS, K64, K32> &T, int s, uint32_t cnt, uin
 // one chunk.  One workgroup of GB_BUCKET_THREADS threads; P <= GB_MAX_P_WIDE.
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint32_t *__restrict__ start, int P,
                                                                       int64_t chunk_rows, uint32_t *__restrict__ cstart,
-                                                                      uint32_t *__restrict__ order)
+                                                                      uint32_t *__restrict__ order,
+                                                                      uint32_t *__restrict__ sfirst)
 {
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     constexpr int PER = GB_MAX_P_WIDE / GB_BUCKET_THREADS;
@@ -1208,6 +1238,7 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint
             cstart[b] = run;
             if (nch[i] > 1) {
                 for (uint32_t j = 0; j < nch[i]; ++j) order[srun + j] = run + j;
+                sfirst[b] = srun;
                 srun += nch[i];
             } else if (nch[i] == 1) {
                 order[nsplit + orun] = run;
@@ -1221,10 +1252,14 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint
 
 // Persistent: one workgroup per CU takes chunks from a queue (order[], via a
 // counter) until none is left, and aggregates each chunk's rows in an LDS
-// table.  A bucket that is one chunk writes its groups out directly; each
-// chunk of a split bucket adds its partial groups to the global table
-// instead (a few device atomics per group and chunk), which the table's emit
-// pass writes out.  The next chunk is taken when a chunk starts, and its
+// table.  A bucket that is one chunk writes its groups out directly.  Each
+// chunk of a split bucket writes its partial groups to its own stretch of
+// the workspace and counts itself done; the bucket's last chunk to finish
+// folds the other chunks' partial groups into its LDS table and writes the
+// bucket's groups out.  (If a chunk of the bucket sent rows to the global
+// table, because its LDS table was full, every partial goes to the global
+// table instead, so that no key is emitted from two places; the table's emit
+// pass writes those.)  The next chunk is taken when a chunk starts, and its
 // first records are loaded during the current chunk's last step, so they
 // arrive while the current chunk writes its groups.  Lanes of a wave that
 // update the same slot are summed across the wave first and added by one
@@ -1233,19 +1268,21 @@ template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint64_t *__restrict__ recs,
                                                                       const uint32_t *__restrict__ start,
                                                                       const uint32_t *__restrict__ cstart,
-                                                                      const uint32_t *__restrict__ order, int P,
+                                                                      const uint32_t *__restrict__ order,
+                                                                      const uint32_t *__restrict__ sfirst, int P,
                                                                       int64_t chunk_rows, const uint32_t *side_cnt,
-                                                                      uint32_t *qctr, gtable g, gq_groups out,
-                                                                      uint32_t *status)
+                                                                      uint32_t *qctr, uint32_t *bdone, uint32_t *bspill,
+                                                                      uint32_t *pcnt, gb_part *part, gtable g,
+                                                                      gq_groups out, uint32_t *status)
 {
     constexpr int SLOTS = bucket_slots<K64, K32>::value;
     __shared__ lds_table<SLOTS, K64, K32> T;
     __shared__ uint32_t scan_smem[GB_BUCKET_THREADS / 64];
     __shared__ unsigned long long s_base;
-    __shared__ uint32_t s_item;
+    __shared__ uint32_t s_item, s_spill, s_last;
     const uint32_t total = cstart[P];
-    // rows [r0, r1) of queue item `item`, and whether its bucket is split
-    auto geom = [&](uint32_t item, int64_t &r0, int64_t &r1, bool &split) {
+    // rows [r0, r1) of queue item `item`, its bucket, and whether that is split
+    auto geom = [&](uint32_t item, int64_t &r0, int64_t &r1, int &bk, bool &split) {
         const uint32_t ch = order[item];
         int b = 0;                                   // the bucket of chunk ch: last b with cstart[b] <= ch
         for (int hi = P - 1; b < hi;) {
@@ -1254,6 +1291,7 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
             else hi = mid - 1;
         }
         split = cstart[b + 1] - cstart[b] > 1;
+        bk = b;
         const int64_t b0 = start[b], b1 = start[b + 1];
         r0 = split ? b0 + static_cast<int64_t>(ch - cstart[b]) * chunk_rows : b0;
         r1 = split ? (r0 + chunk_rows < b1 ? r0 + chunk_rows : b1) : b1;
@@ -1276,20 +1314,23 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
     uint32_t item = s_item;
     if (item >= total) return;                       // same for the whole workgroup
     int64_t r0, r1;
+    int bk;
     bool split;
-    geom(item, r0, r1, split);
+    geom(item, r0, r1, bk, split);
     bool have = false;                               // n*[] hold the first step of this item
     const bool merge = *side_cnt != 0u;              // same value for every thread
     while (true) {
         if (!have) load_step(r0, r1);
         lds_init(T);
+        if (threadIdx.x == 0) s_spill = 0;
         __syncthreads();                             // the table is clear; every thread has read s_item
         if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
         __syncthreads();
         const uint32_t nitem = s_item;
         int64_t nr0 = 0, nr1 = 0;
+        int nbk = 0;
         bool nsplit = false;
-        if (nitem < total) geom(nitem, nr0, nr1, nsplit);
+        if (nitem < total) geom(nitem, nr0, nr1, nbk, nsplit);
         bool have_next = false;
         for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
             int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
@@ -1336,20 +1377,74 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
                 }
                 if (mine) lds_add_split(T, s, q[c], rv[c]);
                 const bool spill = active && s < 0;
+                if (spill) s_spill = 1u;
                 const int64_t gs = g_find<K64, K32>(g, spill, h, k64[c], k32[c], status);
                 if (spill && gs >= 0) g_add(g, gs, 1u, static_cast<uint64_t>(q[c]), rev);
             }
         }
         __syncthreads();
+        bool emit = !split;
         if (split) {
-            for (int s = threadIdx.x; s < SLOTS; s += GB_BUCKET_THREADS) {
-                const bool occ = lds_occupied(T, s);
-                const int64_t k64 = occ ? lds_key64(T, s) : 0;
-                const int32_t k32 = occ ? lds_key32(T, s) : 0;
-                const int64_t gs = g_find<K64, K32>(g, occ, gb_hash(k64, k32), k64, k32, status);
-                if (occ && gs >= 0) g_add(g, gs, T.cnt[s], T.sq[s], lds_split_total(T.lo[s], T.hi[s]));
+            // this chunk's partial groups to its stretch of the workspace
+            constexpr int PER = SLOTS / GB_BUCKET_THREADS;
+            uint32_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) mine += lds_occupied(T, threadIdx.x * PER + i) ? 1u : 0u;
+            uint32_t all;
+            uint32_t pre = gq_block_exclusive_scan<GB_BUCKET_THREADS>(mine, &all, scan_smem);
+            gb_part *dst = part + static_cast<size_t>(item) * SLOTS;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int s = threadIdx.x * PER + i;
+                if (lds_occupied(T, s)) {
+                    const gq_i128 tot = lds_split_total(T.lo[s], T.hi[s]);
+                    dst[pre++] = gb_part{lds_key64(T, s), lds_key32(T, s), T.cnt[s], T.sq[s], tot.lo, tot.hi};
+                }
             }
-        } else {
+            __syncthreads();                         // every partial is written
+            if (threadIdx.x == 0) {
+                pcnt[item] = all;
+                if (s_spill) atomicOr(&bspill[bk], 1u);
+                __threadfence();                     // partials, count and spill flag before the done count
+                const uint32_t nch = cstart[bk + 1] - cstart[bk];
+                s_last = (atomicAdd(&bdone[bk], 1u) + 1 == nch) ? 1u : 0u;
+            }
+            __syncthreads();
+            if (s_last) {                            // the bucket's last chunk: every other chunk is done
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const bool to_global = __hip_atomic_load(&bspill[bk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+                const uint32_t nch = cstart[bk + 1] - cstart[bk];
+                const uint32_t first = sfirst[bk];
+                for (uint32_t j = 0; j < nch; ++j) {
+                    const uint32_t it = first + j;
+                    if (it == item && !to_global) continue;    // its own groups are in the LDS table
+                    const uint32_t cntj = __hip_atomic_load(&pcnt[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const gb_part *src = part + static_cast<size_t>(it) * SLOTS;
+                    for (uint32_t e0 = 0; e0 < cntj; e0 += GB_BUCKET_THREADS) {
+                        const uint32_t e = e0 + threadIdx.x;
+                        const bool act = e < cntj;
+                        gb_part pe{};
+                        if (act) pe = src[e];
+                        const uint64_t h = gb_hash(pe.k64, pe.k32);
+                        const gq_i128 rev{pe.lo, pe.hi};
+                        // into the LDS table (unless the bucket goes to the global table)
+                        int sl = to_global ? -1 : lds_find(T, act, h, pe.k64, pe.k32);
+                        if (act && sl >= 0) {
+                            // the int128 sum as split halves: low 32 bits, then the rest
+                            // (|rev >> 32| < rows * 2^31 fits the 64-bit high sum)
+                            const int64_t hi32 = static_cast<int64_t>((static_cast<uint64_t>(pe.hi) << 32) | (pe.lo >> 32));
+                            lds_add_sums(T, sl, pe.cnt, pe.sq, pe.lo & 0xffffffffull, hi32);
+                        }
+                        const bool gl = act && sl < 0;
+                        const int64_t gs = g_find<K64, K32>(g, gl, h, pe.k64, pe.k32, status);
+                        if (gl && gs >= 0) g_add(g, gs, pe.cnt, pe.sq, rev);
+                    }
+                }
+                emit = !to_global;
+                __syncthreads();                     // the folded table is complete
+            }
+        }
+        if (emit) {
             // emit: each thread owns SLOTS / GB_BUCKET_THREADS consecutive slots
             constexpr int PER = SLOTS / GB_BUCKET_THREADS;
             uint32_t mine = 0;
@@ -1391,8 +1486,10 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
             }
         }
         if (nitem >= total) break;                   // same for the whole workgroup
+        item = nitem;
         r0 = nr0;
         r1 = nr1;
+        bk = nbk;
         split = nsplit;
         have = have_next;
         __syncthreads();                             // the table is read out before it is cleared
@@ -1419,6 +1516,7 @@ struct gb_plan {
     uint64_t gslots;
     int64_t bucket_chunk;   // rows per workgroup of a split bucket
     int64_t bucket_grid;    // bucket-pass workgroups: P plus the most extra chunks n rows can need
+    int64_t split_max;      // the most chunks that split buckets can have
 };
 
 int groupby_fill_percent()
@@ -1461,6 +1559,9 @@ gb_plan make_plan(int64_t n, int64_t max_groups, bool k64, bool k32)
         pl.bucket_chunk = std::max<int64_t>(4 * mean, 65536);
         pl.bucket_chunk = (pl.bucket_chunk + 4095) / 4096 * 4096;
         pl.bucket_grid = pl.P + n / pl.bucket_chunk;
+        // a split bucket has more than bucket_chunk rows and at most
+        // 2 rows / bucket_chunk chunks
+        pl.split_max = 2 * (n / pl.bucket_chunk) + 1;
         if (pl.wide) {                      // P is a multiple of GB_CUS, so of GB_P1
             pl.P2 = pl.P / GB_P1;
             pl.tiles2 = (n + GB_T2 - 1) / GB_T2 + GB_P1;
@@ -1476,6 +1577,11 @@ struct gb_ws {
     uint32_t *start;
     uint32_t *cstart;       // chunks of the bucket pass before each bucket
     uint32_t *order;        // the bucket pass's chunk queue
+    uint32_t *sfirst;       // queue position of a split bucket's first chunk
+    uint32_t *bdone;        // chunks of each bucket finished
+    uint32_t *bspill;       // a chunk of the bucket sent rows to the global table
+    uint32_t *pcnt;         // partial groups of each split chunk
+    void *part;             // the partial groups (split chunks only)
     void *scan_ws;
     uint64_t *recs;         // partitioned rows, narrow records
     uint32_t *side;         // row indices of wide rows
@@ -1495,6 +1601,11 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
     // [32 (GQ_NUM_XCD + 1)] the bucket pass's queue counter; one 128-byte
     // line each
     w.side_cnt = c.take<uint32_t>(32 * (GQ_NUM_XCD + 2));
+    w.g.used = c.take<uint32_t>(32);
+    if (!pl.small) {                        // per bucket: chunks finished, a chunk spilled
+        w.bdone = c.take<uint32_t>(static_cast<size_t>(pl.P));
+        w.bspill = c.take<uint32_t>(static_cast<size_t>(pl.P));
+    }
     w.zero_bytes = c.off;                   // the state words and counters start at zero
     w.g.k64 = c.take<int64_t>(k64 ? S : 1);
     w.g.k32 = c.take<int32_t>(k32 ? S : 1);
@@ -1510,6 +1621,10 @@ gb_ws gb_layout(gq_carver &c, const gb_plan &pl, int64_t n, bool k64, bool k32)
         w.start = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
         w.cstart = c.take<uint32_t>(static_cast<size_t>(pl.P) + 1);
         w.order = c.take<uint32_t>(static_cast<size_t>(pl.bucket_grid));
+        w.sfirst = c.take<uint32_t>(static_cast<size_t>(pl.P));
+        w.pcnt = c.take<uint32_t>(static_cast<size_t>(pl.split_max));
+        w.part = c.take<char>(static_cast<size_t>(pl.split_max) * static_cast<size_t>(k64 ? 3072 : 4096) *
+                              sizeof(gb_part));
         w.scan_ws = c.take<char>(gq_tile_offsets_workspace(pl.ntiles, P1));
         w.recs = c.take<uint64_t>(rows * static_cast<size_t>(pl.words));
         w.side = c.take<uint32_t>(rows);
@@ -1584,16 +1699,16 @@ gq_status run_groupby(gq_ctx *ctx, const gb_args &a, const gb_plan &pl, const gb
                      static_cast<const uint32_t *>(w.side), static_cast<const uint32_t *>(w.side_cnt), w.g,
                      ctx->status_dev));
     GQ_TRY(gq_launch(ctx, "gq_groupby_chunks", gb_chunks_kernel, dim3(1), dim3(GB_BUCKET_THREADS), 0, s,
-                     static_cast<const uint32_t *>(w.start), pl.P, pl.bucket_chunk, w.cstart, w.order));
+                     static_cast<const uint32_t *>(w.start), pl.P, pl.bucket_chunk, w.cstart, w.order, w.sfirst));
     // one workgroup per CU (its LDS table takes most of a CU), each taking
     // chunks from the queue
     const int64_t bgrid = std::min<int64_t>(pl.bucket_grid, static_cast<int64_t>(ctx->num_cus));
     GQ_TRY(gq_launch(ctx, "gq_groupby_bucket", gb_bucket_kernel<K64, K32>, dim3(static_cast<uint32_t>(bgrid)),
                      dim3(GB_BUCKET_THREADS), 0, s, static_cast<const uint64_t *>(w.recs),
                      static_cast<const uint32_t *>(w.start), static_cast<const uint32_t *>(w.cstart),
-                     static_cast<const uint32_t *>(w.order), pl.P, pl.bucket_chunk,
-                     static_cast<const uint32_t *>(w.side_cnt), w.side_cnt + 32 * (GQ_NUM_XCD + 1), w.g, out,
-                     ctx->status_dev));
+                     static_cast<const uint32_t *>(w.order), static_cast<const uint32_t *>(w.sfirst), pl.P,
+                     pl.bucket_chunk, static_cast<const uint32_t *>(w.side_cnt), w.side_cnt + 32 * (GQ_NUM_XCD + 1),
+                     w.bdone, w.bspill, w.pcnt, static_cast<gb_part *>(w.part), w.g, out, ctx->status_dev));
     return gq_launch(ctx, "gq_groupby_emit", gb_table_emit_kernel<K64, K32>, dim3(emit_blocks), dim3(256), 0, s, w.g,
                      out, ctx->status_dev);
 }

@@ -543,10 +543,11 @@ def test_groupby_large_path_wide_rows(ctx, composite, overflow):
 def test_groupby_heavy_keys_split_buckets(ctx, composite, max_groups):
     """Zipf-like heavy keys: one key holds 40% of the rows, others 10% and 5%.
     Their buckets hold far more rows than the mean and are aggregated in
-    chunks by several workgroups whose partial groups merge in the global
-    table; lanes of a wave on the same key combine before their LDS update.
-    Some heavy-key rows are too wide for a narrow record.  Exact against the
-    oracle, with the tile-staged (500K groups) and the chunked (6M) scatter."""
+    chunks by several workgroups; the bucket's last chunk folds the others'
+    partial groups into its LDS table; lanes of a wave on the same key combine
+    before their LDS update.  Some heavy-key rows are too wide for a narrow
+    record.  Exact against the oracle, with the one-level (500K groups) and
+    the two-level (6M) scatter."""
     r = rng(71 + int(composite) + (2 if max_groups > 1_000_000 else 0))
     n = nv = 2_000_000
     keys = np.unique(r.integers(0, 1 << 31, size=200_000)).astype(np.int32)
@@ -574,6 +575,37 @@ def test_groupby_heavy_keys_split_buckets(ctx, composite, max_groups):
                                 max_groups=max_groups)
     assert ctx.status() == gq.GQ_OK
     assert exp["count"].max() >= 0.2 * n
+    _check_groups(res, exp, composite, True)
+
+
+@pytest.mark.parametrize("composite", [False, True])
+def test_groupby_split_bucket_overflowing_lds(ctx, composite):
+    """A bucket that is both split (a key with half of the rows) and too full
+    for its LDS tables (9000 keys hashed into it): its chunks send rows to the
+    global table, so every chunk's partial groups go there too and no key is
+    written out twice.  Exact against the oracle."""
+    r = rng(91 + int(composite))
+    n = nv = 400_000
+    hot = _hot_keys(r, 9000).astype(np.int32)
+    other = np.unique(r.integers(0, 1 << 31, size=20_000)).astype(np.int32)
+    keys = np.concatenate([hot, other])
+    key32 = keys[r.integers(0, len(keys), size=n)]
+    key32[r.random(n) < 0.5] = hot[0]                          # the heavy key, in the crowded bucket
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    if composite:
+        key64 = np.where(np.isin(key32, hot), 0, key32.astype(np.int64) * 5 + 3).astype(np.int64)
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key64=key64, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key64=dev(key64),
+                                key32=dev(key32), max_groups=250_000)
+    else:
+        exp = oracle.groupby(n, qty, price, disc, rowid=rowid, key32=key32)
+        res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(key32),
+                                max_groups=250_000)
+    assert ctx.status() == gq.GQ_OK
+    assert exp["count"].max() >= 0.4 * n
     _check_groups(res, exp, composite, True)
 
 
