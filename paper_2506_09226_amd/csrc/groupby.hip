@@ -150,6 +150,18 @@ GQ_DEV uint32_t lds_home(uint64_t h)
     return static_cast<uint32_t>((static_cast<uint64_t>(static_cast<uint32_t>(h >> 8)) * SLOTS) >> 32);
 }
 
+// Slot s back to empty (its sums to zero).
+template <int SLOTS, bool K64, bool K32>
+GQ_DEV void lds_clear_slot(lds_table<SLOTS, K64, K32> &T, int s)
+{
+    T.word[s] = K64 ? LDS_EMPTY64 : 0ull;
+    if constexpr (K64 && K32) T.k32[s] = static_cast<int32_t>(LDS_EMPTY32);
+    T.cnt[s] = 0;
+    T.sq[s] = 0;
+    T.lo[s] = 0;
+    T.hi[s] = 0;
+}
+
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_init(lds_table<SLOTS, K64, K32> &T)
 {
@@ -635,17 +647,36 @@ __global__ __launch_bounds__(GB_THREADS) void gb_hist_kernel(gb_args a, int P, i
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk_rows;
     if (c0 >= n) return;                                   // past the row count: no counts (the scan skips it)
     const int64_t c1 = c0 + chunk_rows < n ? c0 + chunk_rows : n;
-    for (int64_t base = c0; base < c1; base += TILE) {
-#pragma unroll 4
+    // a tile's keys are loaded together, and the next tile's while this
+    // tile's rows are counted (the row id is read only to filter)
+    bool nv[ITEMS];
+    int64_t nk64[ITEMS];
+    int32_t nk32[ITEMS];
+    auto load_tile = [&](int64_t base) {
+#pragma unroll
         for (int c = 0; c < ITEMS; ++c) {
             const int64_t j = base + c * GB_THREADS + threadIdx.x;
-            if (j < c1 && (!a.filter || row_pass(a, value_row(a, j)))) {   // row id read only to filter
-                int64_t k64;
-                int32_t k32;
-                load_key<K64, K32>(a, j, k64, k32);
-                atomicAdd(&h[gb_bucket(gb_hash(k64, k32), P)], 1u);
-            }
+            nv[c] = j < c1 && (!a.filter || row_pass(a, value_row(a, j)));
+            nk64[c] = 0;
+            nk32[c] = 0;
+            if (nv[c]) load_key<K64, K32>(a, j, nk64[c], nk32[c]);
         }
+    };
+    load_tile(c0);
+    for (int64_t base = c0; base < c1; base += TILE) {
+        bool v[ITEMS];
+        int64_t k64[ITEMS];
+        int32_t k32[ITEMS];
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            v[c] = nv[c];
+            k64[c] = nk64[c];
+            k32[c] = nk32[c];
+        }
+        if (base + TILE < c1) load_tile(base + TILE);
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c)
+            if (v[c]) atomicAdd(&h[gb_bucket(gb_hash(k64[c], k32[c]), P)], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < P; b += GB_THREADS) hist[static_cast<int64_t>(blockIdx.x) * P + b] = h[b];
@@ -1319,9 +1350,9 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
     geom(item, r0, r1, bk, split);
     bool have = false;                               // n*[] hold the first step of this item
     const bool merge = *side_cnt != 0u;              // same value for every thread
+    lds_init(T);                                     // once: each chunk leaves the table empty
     while (true) {
         if (!have) load_step(r0, r1);
-        lds_init(T);
         if (threadIdx.x == 0) s_spill = 0;
         __syncthreads();                             // the table is clear; every thread has read s_item
         if (threadIdx.x == 0) s_item = atomicAdd(qctr, 1u);
@@ -1482,7 +1513,15 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
                 if (occ) {
                     emit_group(out, idx, k64, k32, cnt, sq, lo, hi, status);
                     ++idx;
+                    lds_clear_slot(T, s);            // the table is empty again for the next chunk
                 }
+            }
+        } else {
+            constexpr int PER = SLOTS / GB_BUCKET_THREADS;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int s = threadIdx.x * PER + i;
+                if (lds_occupied(T, s)) lds_clear_slot(T, s);
             }
         }
         if (nitem >= total) break;                   // same for the whole workgroup
