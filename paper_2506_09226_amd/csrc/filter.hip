@@ -72,15 +72,24 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
     const int nt = static_cast<int>(ntiles - t0 < FT_GROUP ? ntiles - t0 : FT_GROUP);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint32_t cnt = 0;                                      // this thread's matches over the group
+    // the next tile's values are loaded while this tile's are tested
+    T nv[FT_ITEMS];
+    auto load_tile = [&](int i) {
+        const int64_t base = (t0 + i) * FT_TILE;
+#pragma unroll
+        for (int c = 0; c < FT_ITEMS; ++c) {
+            const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
+            nv[c] = 0;
+            if (i < nt && e < n) nv[c] = col[HAS_SEL ? static_cast<int64_t>(sel_in[e]) : e];
+        }
+    };
+    load_tile(0);
     for (int i = 0; i < nt; ++i) {
         const int64_t base = (t0 + i) * FT_TILE;
         T v[FT_ITEMS];
 #pragma unroll
-        for (int c = 0; c < FT_ITEMS; ++c) {
-            const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
-            v[c] = 0;
-            if (e < n) v[c] = col[HAS_SEL ? static_cast<int64_t>(sel_in[e]) : e];
-        }
+        for (int c = 0; c < FT_ITEMS; ++c) v[c] = nv[c];
+        if (i + 1 < nt) load_tile(i + 1);
 #pragma unroll
         for (int c = 0; c < FT_ITEMS; ++c) {
             const int64_t e = base + c * FT_THREADS + wave * 64 + lane;
@@ -106,7 +115,7 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
         uint32_t mine = static_cast<uint32_t>(bits[i][threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32));
         uint32_t total;
         uint32_t pos =
-            gq_block_exclusive_scan<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+            gq_block_exclusive_scan_lds<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
         const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * 32;
         while (mine) {
             const int k = __builtin_ctz(mine);
@@ -114,10 +123,10 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
             const int64_t e = row0 + k;
             stage[pos++] = HAS_SEL ? sel_in[e] : static_cast<int32_t>(e);
         }
-        __syncthreads();
+        gq_lds_barrier();                                  // (LDS only: the last tile's stores stay in flight)
         for (uint32_t k = threadIdx.x; k < total; k += FT_THREADS) out[goff + k] = stage[k];
         goff += total;
-        __syncthreads();                                   // stage[] is free for the next tile
+        gq_lds_barrier();                                  // stage[] is free for the next tile
     }
     if (g == ngroups - 1 && threadIdx.x == 0) *n_out = goff;
 }

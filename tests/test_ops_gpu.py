@@ -410,6 +410,28 @@ def test_groupby_row_filter(ctx, groups):
     _check_groups(res, exp, False, True)
 
 
+@pytest.mark.parametrize("n", [32_767, 300_003])
+def test_groupby_large_path_key32_by_rowid_filtered(ctx, n):
+    """Large path with the key read at the value row (key32[rowid[j]]) and a
+    row filter: chunk and tile edges (32K-row chunks, 4096-row tiles) with a
+    ragged tail, every group exact."""
+    r = rng(47)
+    nv = 2 * n + 5
+    rowid = r.integers(0, nv, size=n).astype(np.int32)
+    keyv = r.integers(0, 20_000, size=nv).astype(np.int32)
+    qty = r.integers(1, 51, size=nv).astype(np.int64)
+    price = r.integers(100, 10_000_001, size=nv).astype(np.int64)
+    disc = r.integers(0, 11, size=nv).astype(np.int64)
+    fcol = r.integers(0, 2557, size=nv).astype(np.int32)
+    keep = np.nonzero(fcol[rowid] < 1500)[0]
+    exp = oracle.groupby(len(keep), qty, price, disc, rowid=rowid[keep], key32=keyv, key32_by_rowid=True)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), rowid=dev(rowid), key32=dev(keyv),
+                            key32_by_rowid=True, max_groups=40_000, filter_col=dev(fcol), filter_lo=0,
+                            filter_hi=1500)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, True)
+
+
 def test_groupby_no_key_and_empty(ctx):
     n = 10_000
     _, _, _, qty, price, disc = _gb_inputs(n, n, 4, 1)
