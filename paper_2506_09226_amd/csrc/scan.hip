@@ -75,12 +75,13 @@ gq_status gq_scan_u32(gq_ctx *ctx, uint32_t *data, int64_t n, void *ws, hipStrea
 //   start[b]     = sum_{b' < b} total[b'],   start[P] = sum of all counts.
 //
 // Four small kernels, every access coalesced across buckets: per-chunk column
-// sums (a chunk = TO_CHUNK tiles), a scan of those sums down each column, an
-// exclusive scan of the bucket totals, and the final per-tile offsets.
+// sums, a scan of those sums down each column, an exclusive scan of the bucket
+// totals, and the final per-tile offsets.  A chunk is 32 to 256 tiles, sized
+// for about 192 chunks: enough workgroups for the two column passes, and a
+// short walk down each column for the one-workgroup scan between them.
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int TO_CHUNK = 256;
 constexpr int TO_THREADS = 256;
 constexpr int TO_MAX_P = 8192;
 constexpr int TO_START_THREADS = 1024;
@@ -88,6 +89,13 @@ constexpr int TO_START_THREADS = 1024;
 // Column loops load TO_BATCH counts into registers before using them, so a
 // thread keeps that many independent loads in flight.
 constexpr int TO_BATCH = 32;
+
+int64_t to_chunk_tiles(int64_t ntiles)
+{
+    int64_t c = 32;
+    while (c < 256 && c * 192 < ntiles) c *= 2;
+    return c;
+}
 
 // Tiles that hold counts: all ntiles, or those the device row count reaches.
 GQ_DEV int64_t to_live_tiles(int64_t ntiles, gq_tile_count live)
@@ -100,14 +108,15 @@ GQ_DEV int64_t to_live_tiles(int64_t ntiles, gq_tile_count live)
 }
 
 __global__ __launch_bounds__(TO_THREADS) void to_chunk_sum_kernel(const uint32_t *__restrict__ cnt, int64_t ntiles,
-                                                                  int P, uint32_t *__restrict__ csum, gq_tile_count live)
+                                                                  int P, int64_t chunk, uint32_t *__restrict__ csum,
+                                                                  gq_tile_count live)
 {
     ntiles = to_live_tiles(ntiles, live);
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * TO_THREADS + threadIdx.x;
     if (b >= P) return;
-    const int64_t t0 = c * TO_CHUNK;
-    const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
+    const int64_t t0 = c * chunk;
+    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
     uint32_t s = 0;
     for (int64_t t = t0; t < t1; t += TO_BATCH) {
         uint32_t x[TO_BATCH];
@@ -160,15 +169,15 @@ __global__ __launch_bounds__(TO_START_THREADS) void to_bucket_start_kernel(const
 }
 
 __global__ __launch_bounds__(TO_THREADS) void to_final_kernel(uint32_t *__restrict__ cnt, int64_t ntiles, int P,
-                                                              const uint32_t *__restrict__ csum,
+                                                              int64_t chunk, const uint32_t *__restrict__ csum,
                                                               const uint32_t *__restrict__ start, gq_tile_count live)
 {
     ntiles = to_live_tiles(ntiles, live);
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * TO_THREADS + threadIdx.x;
     if (b >= P) return;
-    const int64_t t0 = c * TO_CHUNK;
-    const int64_t t1 = t0 + TO_CHUNK < ntiles ? t0 + TO_CHUNK : ntiles;
+    const int64_t t0 = c * chunk;
+    const int64_t t1 = t0 + chunk < ntiles ? t0 + chunk : ntiles;
     uint32_t run = start[b] + csum[c * P + b];
     for (int64_t t = t0; t < t1; t += TO_BATCH) {
         uint32_t x[TO_BATCH];
@@ -187,7 +196,8 @@ __global__ __launch_bounds__(TO_THREADS) void to_final_kernel(uint32_t *__restri
 size_t gq_tile_offsets_workspace(int64_t ntiles, int P)
 {
     gq_carver c(nullptr);
-    const int64_t nchunks = (ntiles + TO_CHUNK - 1) / TO_CHUNK;
+    const int64_t chunk = to_chunk_tiles(ntiles);
+    const int64_t nchunks = (ntiles + chunk - 1) / chunk;
     c.take<uint32_t>(static_cast<size_t>((nchunks > 0 ? nchunks : 1) * P));
     c.take<uint32_t>(static_cast<size_t>(P));
     return c.bytes();
@@ -200,16 +210,17 @@ gq_status gq_tile_offsets(gq_ctx *ctx, uint32_t *cnt, int64_t ntiles, int P, uin
     if (live && live->tile_rows < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_tile_offsets: bad tile rows");
     if (P < 1 || P > TO_MAX_P || ntiles < 1) return gq_fail(ctx, GQ_ERR_INVALID_ARG, "gq_tile_offsets: bad shape");
     gq_carver c(ws);
-    const int64_t nchunks = (ntiles + TO_CHUNK - 1) / TO_CHUNK;
+    const int64_t chunk = to_chunk_tiles(ntiles);
+    const int64_t nchunks = (ntiles + chunk - 1) / chunk;
     uint32_t *csum = c.take<uint32_t>(static_cast<size_t>(nchunks * P));
     uint32_t *total = c.take<uint32_t>(static_cast<size_t>(P));
     const dim3 grid2(static_cast<uint32_t>(nchunks), static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
     const dim3 grid1(static_cast<uint32_t>((P + TO_THREADS - 1) / TO_THREADS));
     GQ_TRY(gq_launch(ctx, name, to_chunk_sum_kernel, grid2, dim3(TO_THREADS), 0, s,
-                     static_cast<const uint32_t *>(cnt), ntiles, P, csum, lv));
+                     static_cast<const uint32_t *>(cnt), ntiles, P, chunk, csum, lv));
     GQ_TRY(gq_launch(ctx, name, to_chunk_scan_kernel, grid1, dim3(TO_THREADS), 0, s, csum, nchunks, P, total));
     GQ_TRY(gq_launch(ctx, name, to_bucket_start_kernel, dim3(1), dim3(TO_START_THREADS), 0, s,
                      static_cast<const uint32_t *>(total), P, start));
-    return gq_launch(ctx, name, to_final_kernel, grid2, dim3(TO_THREADS), 0, s, cnt, ntiles, P,
+    return gq_launch(ctx, name, to_final_kernel, grid2, dim3(TO_THREADS), 0, s, cnt, ntiles, P, chunk,
                      static_cast<const uint32_t *>(csum), static_cast<const uint32_t *>(start), lv);
 }
