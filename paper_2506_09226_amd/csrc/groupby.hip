@@ -556,6 +556,7 @@ constexpr int GB_MAX_P = 1024;                      // buckets of the tile-stage
 constexpr int GB_MAX_P_WIDE = 8192;                 // buckets of the two-level scatter
 constexpr int64_t GB_CUS = 256;                     // compute units of the MI355X
 constexpr int GB_BUCKET_ITEMS = 4;
+constexpr int GB_COMBINE_LANES = 8;                 // lanes on one slot above which a wave sums them first
 
 template <bool K64, bool K32>
 struct gb_fmt {
@@ -1292,9 +1293,10 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_chunks_kernel(const uint
 // table instead, so that no key is emitted from two places; the table's emit
 // pass writes those.)  The next chunk is taken when a chunk starts, and its
 // first records are loaded during the current chunk's last step, so they
-// arrive while the current chunk writes its groups.  Lanes of a wave that
-// update the same slot are summed across the wave first and added by one
-// lane, so a heavy key costs one LDS update per wave rather than one per row.
+// arrive while the current chunk writes its groups.  When more than
+// GB_COMBINE_LANES lanes of a wave update the same slot, they are summed
+// across the wave first and added by one lane, so a heavy key costs one LDS
+// update per wave rather than one per row.
 template <bool K64, bool K32>
 __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint64_t *__restrict__ recs,
                                                                       const uint32_t *__restrict__ start,
@@ -1396,8 +1398,10 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
                     const int sl = __builtin_amdgcn_readlane(s, lead);
                     const bool in = mine && s == sl;
                     const uint64_t same = gq_ballot(in);
-                    if (__popcll(same) > 1) {
-                        const uint32_t cn = gq_wave_sum<uint32_t>(in ? 1u : 0u);
+                    // worth the cross-lane sums only for a key that fills much of
+                    // the wave (a few equal lanes cost less as plain LDS atomics)
+                    if (__popcll(same) > GB_COMBINE_LANES) {
+                        const uint32_t cn = static_cast<uint32_t>(__popcll(same));
                         const uint64_t sq = gq_wave_sum<uint64_t>(in ? static_cast<uint64_t>(q[c]) : 0ull);
                         const uint64_t lo = gq_wave_sum<uint64_t>(
                             in ? static_cast<uint64_t>(static_cast<uint32_t>(static_cast<uint64_t>(rv[c]))) : 0ull);
