@@ -410,6 +410,27 @@ def test_groupby_row_filter(ctx, groups):
     _check_groups(res, exp, False, True)
 
 
+def test_groupby_large_path_edges(ctx):
+    """The large path (bucketed) with no key at all (one group), with a device
+    row count of zero, and with a device row count well below the bound
+    (only the first rows count)."""
+    n = 100_003
+    _, key32, _, qty, price, disc = _gb_inputs(n, n, 12, 3000)
+    exp = oracle.groupby(n, qty, price, disc)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), max_groups=5000)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, False)
+    n_dev = torch.zeros(1, dtype=torch.int64, device="cuda")
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), n_dev=n_dev, key32=dev(key32), max_groups=5000)
+    assert ctx.status() == gq.GQ_OK and int(res.n_groups.item()) == 0
+    part = 70_001
+    n_dev.fill_(part)
+    exp = oracle.groupby(part, qty, price, disc, key32=key32)
+    res = gq.gq_groupby_agg(ctx, dev(qty), dev(price), dev(disc), n_dev=n_dev, key32=dev(key32), max_groups=5000)
+    assert ctx.status() == gq.GQ_OK
+    _check_groups(res, exp, False, True)
+
+
 @pytest.mark.parametrize("n", [32_767, 300_003])
 def test_groupby_large_path_key32_by_rowid_filtered(ctx, n):
     """Large path with the key read at the value row (key32[rowid[j]]) and a
