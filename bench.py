@@ -226,6 +226,32 @@ def cpu_baseline(w, shard_rows: int, threads: int) -> dict:
                             "sample": f"one shard of {shard_rows:,} rows, {dt1:.1f} s"}}
 
 
+def copy_bandwidth(gib: int = 2, reps: int = 5) -> dict:
+    """Read + write rate of a plain device-to-device copy of `gib` GiB,
+    timed on the same box and in the same process as the steps: the practical
+    ceiling that a bandwidth-bound kernel's fraction of the peak is set against."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * n * 4
+    del src, dst
+    _release()
+    gbs = moved / (ms * 1e6)
+    return {"bytes_per_copy": moved, "ms": round(ms, 4), "GB/s": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def _timed(fn, steps, warm, stream):
     import torch
     for _ in range(warm):
@@ -283,6 +309,8 @@ def main():
                     help="variant: skip the radix partition and run filter/join/group-by on the input order")
     ap.add_argument("--no-clocks", action="store_true",
                     help="record no GPU clocks (rocm-smi is not started; for runs under a profiler)")
+    ap.add_argument("--no-copy-ref", action="store_true",
+                    help="plain form: skip the 2 GiB device copy timed after the steps (the practical ceiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (3 times) to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -383,6 +411,7 @@ def bench_plain(args) -> dict:
     ctx.set_timing(False)
     ctx.raise_status()
     clk_steps = gpu_clocks()                   # read right after the timed steps, still in their clock state
+    copy_ref = None if args.no_copy_ref else copy_bandwidth()
     print(f"# {args.steps} steps: {ms_step:.3f} ms/step (host wall {1e3 * wall / args.steps:.3f} ms/step)",
           file=sys.stderr, flush=True)
     by = algorithmic_bytes(w.fact.n, w.dim_m, s_n, groups, 100, partition=not args.no_partition)
@@ -438,6 +467,7 @@ def bench_plain(args) -> dict:
         "roofline": roofline,
         "cpu_baseline": None,
         "gpu_clocks": {"after_plain_steps": clk_steps},
+        "copy_ref": copy_ref,
     }
     del pl, fact, dim
     ctx.close()
