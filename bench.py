@@ -63,7 +63,7 @@ OP_KERNELS = {
     "filter": ["gq_filter"],
     "join_build": ["gq_join_build_init", "gq_join_build_insert", "gq_join_build_part_hist",
                    "gq_join_build_part_scan", "gq_join_build_part_offsets", "gq_join_build_part_scatter",
-                   "gq_join_build_bounds", "gq_join_build_regions", "gq_join_build_overflow"],
+                   "gq_join_build_split", "gq_join_build_regions", "gq_join_build_overflow"],
     "join_probe": ["gq_join_probe", "gq_join_probe_split", "gq_join_probe_plan", "gq_join_probe_regions",
                    "gq_join_probe_compact"],
     "groupby": ["gq_groupby_hist", "gq_groupby_scan", "gq_groupby_scatter", "gq_groupby_tiles2", "gq_groupby_hist2",

@@ -11,9 +11,10 @@
 // stores the payload (the probe runs in a later kernel, so it sees the store).
 //
 // Build, large tables (device-memory CAS runs at only ~10 G/s on MI355X): the
-// build rows are radix-partitioned (stable LSD passes of the partition
-// operator) by the region of their home slot, a region being 4096 consecutive
-// slots; one workgroup per region inserts its keys into an LDS copy of the
+// build rows are sorted by the region of their home slot, a region being
+// 4096 consecutive slots: the partition operator by the top 8 hash bits,
+// then, for more than 256 regions, one workgroup per bucket splitting it by
+// the remaining region bits; one workgroup per region inserts its keys into an LDS copy of the
 // region with LDS compare-and-swap and writes the region out linearly.  A key
 // whose probe runs past its region's last slot goes to an overflow list and is
 // inserted afterwards by device CAS from the first slot of the next region,
@@ -124,22 +125,121 @@ __global__ __launch_bounds__(256) void jt_insert_kernel(void *table, int log2_sl
 
 constexpr int JR_BITS = 12;                         // 4096 slots per region (64 KiB)
 constexpr int JR_SLOTS = 1 << JR_BITS;
-constexpr int JR_MAX_REGION_BITS = 16;              // two 8-bit partition passes at most
+constexpr int JR_MAX_REGION_BITS = 16;              // two 8-bit levels at most
 constexpr int64_t JR_MIN_KEYS = 1 << 18;            // below this the CAS build is used
 
-// Start offset of every region in the region-sorted keys: roff[r] = first i
-// with region(keys[i]) >= r, roff[2^g] = m.  Each entry is written once, by
-// the element at which the region sequence steps past it.
-__global__ __launch_bounds__(256) void jt_region_bounds_kernel(const int64_t *__restrict__ keys, int64_t m, int g,
-                                                               int64_t *__restrict__ roff)
+// Second level of the region sort.  The first level is a radix partition by
+// the top JS_HIGH bits of the hash; workgroup b takes that partition's bucket
+// b and splits it by the next g - JS_HIGH bits, so that the keys end up
+// ordered by region (the top g bits) and roff[r] is the first key of region
+// r.  It counts its bucket's sub-buckets first (one read of the keys), which
+// gives both the region starts and the output cursors, then moves the bucket
+// tile by tile: a tile's rows are grouped by sub-bucket in LDS and each group
+// is written at its cursor as one run.  Rows keep no particular order inside
+// a region; the region kernel's inserts do not depend on it.
+constexpr int JS_HIGH = 8;                           // bits of the first level
+constexpr int JS_THREADS = 1024;
+constexpr int JS_ITEMS = 8;
+constexpr int JS_TILE = JS_THREADS * JS_ITEMS;
+
+GQ_DEV uint32_t js_sub(int64_t k, int g, uint32_t smask)
 {
-    const int64_t nr = int64_t(1) << g;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i <= m;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t prev =
-            i == 0 ? -1 : static_cast<int64_t>(gq_fmix64(static_cast<uint64_t>(keys[i - 1])) >> (64 - g));
-        const int64_t cur = i == m ? nr : static_cast<int64_t>(gq_fmix64(static_cast<uint64_t>(keys[i])) >> (64 - g));
-        for (int64_t r = prev + 1; r <= cur; ++r) roff[r] = i;
+    return static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k)) >> (64 - g)) & smask;
+}
+
+__global__ __launch_bounds__(JS_THREADS) void jt_split_kernel(const int64_t *__restrict__ k1,
+                                                              const int32_t *__restrict__ p1,
+                                                              const int64_t *__restrict__ bstart, int64_t m, int g,
+                                                              int64_t *__restrict__ k2, int32_t *__restrict__ p2,
+                                                              int64_t *__restrict__ roff)
+{
+    __shared__ uint32_t cnt[1 << JS_HIGH];           // sub-bucket sizes, then a tile's counts
+    __shared__ uint32_t tstart[1 << JS_HIGH];        // a tile's sub-bucket starts in the stage
+    __shared__ int64_t cur[1 << JS_HIGH];            // output cursor of each sub-bucket
+    __shared__ uint32_t scan_smem[JS_THREADS / 64];
+    __shared__ uint8_t lsub[JS_TILE];
+    __shared__ int64_t sk[JS_TILE];
+    __shared__ int32_t sp[JS_TILE];
+    const int sb = g - JS_HIGH;                      // 1..8 sub-bucket bits
+    const uint32_t S = 1u << sb, smask = S - 1;
+    const int tid = threadIdx.x;
+    const int64_t b0 = bstart[blockIdx.x], b1 = bstart[blockIdx.x + 1];
+
+    for (uint32_t i = tid; i < S; i += JS_THREADS) cnt[i] = 0;
+    __syncthreads();
+    for (int64_t i0 = b0; i0 < b1; i0 += 2 * JS_TILE) {
+        int64_t kk[2 * JS_ITEMS];
+#pragma unroll
+        for (int c = 0; c < 2 * JS_ITEMS; ++c) {
+            const int64_t e = i0 + c * JS_THREADS + tid;
+            kk[c] = e < b1 ? k1[e] : 0;
+        }
+#pragma unroll
+        for (int c = 0; c < 2 * JS_ITEMS; ++c)
+            if (i0 + c * JS_THREADS + tid < b1) atomicAdd(&cnt[js_sub(kk[c], g, smask)], 1u);
+    }
+    __syncthreads();
+    uint32_t total;
+    const uint32_t excl = gq_block_exclusive_scan<JS_THREADS>(static_cast<uint32_t>(tid) < S ? cnt[tid] : 0u,
+                                                              &total, scan_smem);
+    if (static_cast<uint32_t>(tid) < S) {
+        cur[tid] = b0 + excl;
+        roff[(static_cast<int64_t>(blockIdx.x) << sb) + tid] = b0 + excl;
+        cnt[tid] = 0;
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) roff[static_cast<int64_t>(gridDim.x) << sb] = m;
+
+    int64_t k[JS_ITEMS];
+    int32_t p[JS_ITEMS];
+    auto load_tile = [&](int64_t i0) {
+#pragma unroll
+        for (int c = 0; c < JS_ITEMS; ++c) {
+            const int64_t e = i0 + c * JS_THREADS + tid;
+            const bool v = e < b1;
+            k[c] = v ? k1[e] : 0;
+            p[c] = v ? p1[e] : 0;
+        }
+    };
+    if (b0 < b1) load_tile(b0);
+    __syncthreads();
+    for (int64_t i0 = b0; i0 < b1; i0 += JS_TILE) {
+        uint32_t l[JS_ITEMS], rank[JS_ITEMS];
+#pragma unroll
+        for (int c = 0; c < JS_ITEMS; ++c) {
+            l[c] = js_sub(k[c], g, smask);
+            if (i0 + c * JS_THREADS + tid < b1) rank[c] = atomicAdd(&cnt[l[c]], 1u);
+        }
+        gq_lds_barrier();
+        uint32_t tot;
+        const uint32_t st = gq_block_exclusive_scan_lds<JS_THREADS>(
+            static_cast<uint32_t>(tid) < S ? cnt[tid] : 0u, &tot, scan_smem);
+        if (static_cast<uint32_t>(tid) < S) tstart[tid] = st;
+        gq_lds_barrier();
+#pragma unroll
+        for (int c = 0; c < JS_ITEMS; ++c) {
+            if (i0 + c * JS_THREADS + tid < b1) {
+                const uint32_t q = tstart[l[c]] + rank[c];
+                sk[q] = k[c];
+                sp[q] = p[c];
+                lsub[q] = static_cast<uint8_t>(l[c]);
+            }
+        }
+        const int64_t next = i0 + JS_TILE;
+        if (next < b1) load_tile(next);              // in flight while this tile is written
+        gq_lds_barrier();
+        const uint32_t count = static_cast<uint32_t>(b1 - i0 < JS_TILE ? b1 - i0 : JS_TILE);
+        for (uint32_t q = tid; q < count; q += JS_THREADS) {
+            const uint32_t x = lsub[q];
+            const int64_t dst = cur[x] + (q - tstart[x]);
+            k2[dst] = sk[q];
+            p2[dst] = sp[q];
+        }
+        gq_lds_barrier();
+        if (static_cast<uint32_t>(tid) < S) {
+            cur[tid] += cnt[tid];
+            cnt[tid] = 0;
+        }
+        gq_lds_barrier();
     }
 }
 
@@ -341,23 +441,18 @@ gq_status region_build(gq_ctx *ctx, const int64_t *key, const int32_t *payload, 
     static const gq_part_names nm{"gq_join_build_part_hist", "gq_join_build_part_scan", "gq_join_build_part_offsets",
                                   "gq_join_build_part_scatter"};
     GQ_TRY(gq_zero(ctx, w.ovf_cnt, 64, s));
-    if (g <= 8) {
-        void *in[1] = {const_cast<int32_t *>(payload)};
+    void *in[1] = {const_cast<int32_t *>(payload)};
+    if (g <= JS_HIGH) {                             // one pass: its bucket starts are the region starts
         void *out[1] = {w.p2};
-        GQ_TRY(gq_partition_bits(ctx, key, m, g, 64 - g, 1, in, &pbytes, w.k2, out, w.offsets, w.part_ws, s, nm, 8));
-    } else {                                        // LSD: low digit first, both passes stable
-        const int d1 = g / 2, d2 = g - d1;
-        void *in1[1] = {const_cast<int32_t *>(payload)};
-        void *out1[1] = {w.p1};
-        GQ_TRY(gq_partition_bits(ctx, key, m, d1, 64 - g, 1, in1, &pbytes, w.k1, out1, w.offsets, w.part_ws, s, nm, 8));
-        void *in2[1] = {w.p1};
-        void *out2[1] = {w.p2};
-        GQ_TRY(gq_partition_bits(ctx, w.k1, m, d2, 64 - d2, 1, in2, &pbytes, w.k2, out2, w.offsets, w.part_ws, s, nm, 8));
+        GQ_TRY(gq_partition_bits(ctx, key, m, g, 64 - g, 1, in, &pbytes, w.k2, out, w.roff, w.part_ws, s, nm, 8));
+    } else {                                        // the top JS_HIGH bits, then each bucket by the rest
+        void *out[1] = {w.p1};
+        GQ_TRY(gq_partition_bits(ctx, key, m, JS_HIGH, 64 - JS_HIGH, 1, in, &pbytes, w.k1, out, w.offsets, w.part_ws,
+                                 s, nm, 8));
+        GQ_TRY(gq_launch(ctx, "gq_join_build_split", jt_split_kernel, dim3(1u << JS_HIGH), dim3(JS_THREADS), 0, s,
+                         static_cast<const int64_t *>(w.k1), static_cast<const int32_t *>(w.p1),
+                         static_cast<const int64_t *>(w.offsets), m, g, w.k2, w.p2, w.roff));
     }
-    uint64_t bb = (static_cast<uint64_t>(m) + 256) / 256;
-    if (bb > 8192) bb = 8192;
-    GQ_TRY(gq_launch(ctx, "gq_join_build_bounds", jt_region_bounds_kernel, dim3(static_cast<uint32_t>(bb)), dim3(256),
-                     0, s, static_cast<const int64_t *>(w.k2), m, g, w.roff));
     const int64_t nregions = int64_t(1) << g;
     const uint32_t rgrid = static_cast<uint32_t>(std::min<int64_t>(nregions, int64_t(ctx->num_cus) * 3));
     GQ_TRY(gq_launch(ctx, "gq_join_build_regions", jt_region_kernel, dim3(rgrid), dim3(JR_THREADS), 0, s, table, L,

@@ -180,11 +180,14 @@ def build_path(request, monkeypatch):
 
 
 @pytest.mark.parametrize("build_path", ["cas", "region"], indirect=True)
-@pytest.mark.parametrize("m,lf", [(300_000, 0.5), (1_200_000, 0.5), (900_000, 0.9), (70_000, 0.9)])
+@pytest.mark.parametrize("m,lf", [(300_000, 0.5), (1_200_000, 0.5), (900_000, 0.9), (70_000, 0.9),
+                                  (300_000, 0.2), (2_000_000, 0.0075)])
 def test_join_build_paths(ctx, build_path, m, lf):
-    """Both builds (device CAS; LDS regions after a radix partition, including
-    the two-pass case and region overflow at load factor 0.9) give tables on
-    which the probe equals the oracle."""
+    """Both builds (device CAS; LDS regions after a radix sort by region)
+    give tables on which the probe equals the oracle: regions sorted in one
+    pass (2^8 regions and fewer), in two levels with 1, 2 and 8 bits in the
+    second (2^9, 2^10 and 2^16 regions), and with region overflow at load
+    factor 0.9."""
     r = rng(m)
     bkey, bpay = _dim(m, m + 1)
     n = 400_000
