@@ -25,6 +25,7 @@
 // claiming lane always finishes first.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "gq_device.h"
 #include "gq_internal.h"
@@ -101,20 +102,21 @@ GQ_DEV gb_row<K64, K32> load_row(const gb_args &a, int64_t j)
 }
 
 // ----------------------------------------------------------------- LDS table
-// Every table has one 64-bit key word per slot, claimed by a single
-// compare-and-swap.  Without key64 it is (key32 << 32) | 1 (0 = empty), so a
-// claim publishes the whole key at once.  With key64 it is the key64 itself
-// (LDS_EMPTY64 = empty); a composite key's key32 sits in a second word
-// (LDS_EMPTY32 until the claiming lane writes it), so a slot whose key64
-// matches and whose key32 is still empty is being claimed, and a lookup reads
-// it again.  A row whose key part equals an empty marker never enters an LDS
-// table: it goes to the global table, which has its own claiming state.
+// Every table has one key word per slot, claimed by a single
+// compare-and-swap.  Without key64 it is the 32-bit key32 itself
+// (LDS_EMPTY32 = empty), so a claim publishes the whole key at once.  With
+// key64 it is the 64-bit key64 (LDS_EMPTY64 = empty); a composite key's key32
+// sits in a second word (LDS_EMPTY32 until the claiming lane writes it), so a
+// slot whose key64 matches and whose key32 is still empty is being claimed,
+// and a lookup reads it again.  A row whose key part equals an empty marker
+// never enters an LDS table: it goes to the global table, which has its own
+// claiming state.
 constexpr uint64_t LDS_EMPTY64 = 0x8000000000000000ull;
 constexpr uint32_t LDS_EMPTY32 = 0x80000000u;
 
 template <int SLOTS, bool K64, bool K32>
 struct lds_table {
-    uint64_t word[SLOTS];
+    alignas(16) std::conditional_t<K64, uint64_t, uint32_t> word[SLOTS];
     int32_t k32[(K64 && K32) ? SLOTS : 1];
     uint32_t cnt[SLOTS];
     uint64_t sq[SLOTS];
@@ -126,14 +128,14 @@ template <int SLOTS, bool K64, bool K32>
 GQ_DEV bool lds_occupied(const lds_table<SLOTS, K64, K32> &T, int s)
 {
     if constexpr (K64) return T.word[s] != LDS_EMPTY64;
-    else return T.word[s] != 0ull;
+    else return T.word[s] != LDS_EMPTY32;
 }
 
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV int32_t lds_key32(const lds_table<SLOTS, K64, K32> &T, int s)
 {
     if constexpr (K64) return K32 ? T.k32[s] : 0;
-    else return static_cast<int32_t>(static_cast<uint32_t>(T.word[s] >> 32));
+    else return static_cast<int32_t>(T.word[s]);
 }
 
 template <int SLOTS, bool K64, bool K32>
@@ -154,7 +156,8 @@ GQ_DEV uint32_t lds_home(uint64_t h)
 template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_clear_slot(lds_table<SLOTS, K64, K32> &T, int s)
 {
-    T.word[s] = K64 ? LDS_EMPTY64 : 0ull;
+    if constexpr (K64) T.word[s] = LDS_EMPTY64;
+    else T.word[s] = LDS_EMPTY32;
     if constexpr (K64 && K32) T.k32[s] = static_cast<int32_t>(LDS_EMPTY32);
     T.cnt[s] = 0;
     T.sq[s] = 0;
@@ -166,7 +169,8 @@ template <int SLOTS, bool K64, bool K32>
 GQ_DEV void lds_init(lds_table<SLOTS, K64, K32> &T)
 {
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
-        T.word[s] = K64 ? LDS_EMPTY64 : 0ull;
+        if constexpr (K64) T.word[s] = LDS_EMPTY64;
+        else T.word[s] = LDS_EMPTY32;
         if constexpr (K64 && K32) T.k32[s] = static_cast<int32_t>(LDS_EMPTY32);
         T.cnt[s] = 0;
         T.sq[s] = 0;
@@ -184,35 +188,39 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     int probes = 0, found = -1;
     bool done = !active;
     if constexpr (!K64) {
-        // Linear probing over groups of four slots: the four words of a group
-        // are read together (four independent 64-bit loads), the key is
-        // looked for in all of them, and a missing key claims the group's
-        // first empty slot with one compare-and-swap (re-reading the group if
-        // another lane took that slot first).  A key therefore sits in the
-        // first group from its home group that had room when it arrived, and
-        // slots never empty again, so a lookup may stop at the first group
-        // with an empty slot.  The wave-uniform loop runs as long as the
-        // longest chain of the wave, in groups instead of slots.
-        const unsigned long long want = (static_cast<unsigned long long>(static_cast<uint32_t>(k32)) << 32) | 1ull;
+        // Linear probing over groups of four slots: the four 32-bit words of
+        // a group are read together (one 16-byte load), the key is looked for
+        // in all of them, and a missing key claims the group's first empty
+        // slot with one compare-and-swap (re-reading the group if another
+        // lane took that slot first).  A key therefore sits in the first group
+        // from its home group that had room when it arrived, and slots never
+        // empty again, so a lookup may stop at the first group with an empty
+        // slot.  The wave-uniform loop runs as long as the longest chain of
+        // the wave, in groups instead of slots.
+        if (static_cast<uint32_t>(k32) == LDS_EMPTY32) done = true;   // the marker: the global table takes the row
+        const uint32_t want = static_cast<uint32_t>(k32);
         uint32_t g = s >> 2;
         while (__any(!done)) {
             if (!done) {
-                unsigned long long *gp = reinterpret_cast<unsigned long long *>(&T.word[4 * g]);
-                unsigned long long w[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) w[i] = __hip_atomic_load(gp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                uint32_t *gp = &T.word[4 * g];
+                // one 16-byte read; each word is read whole, which is all the
+                // claim protocol needs (a word only ever goes from empty to a key)
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                typedef const volatile __attribute__((address_space(3))) u32x4 lds_u32x4;
+                const u32x4 wv = *(lds_u32x4 *)(gp);
+                const uint32_t w[4] = {wv.x, wv.y, wv.z, wv.w};
                 int hit = -1, empty = -1;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
                     if (w[i] == want) hit = i;
-                    if (w[i] == 0ull) empty = i;
+                    if (w[i] == LDS_EMPTY32) empty = i;
                 }
                 if (hit >= 0) {
                     found = static_cast<int>(4 * g) + hit;
                     done = true;
                 } else if (empty >= 0) {
-                    const unsigned long long prev = atomicCAS(gp + empty, 0ull, want);
-                    if (prev == 0ull || prev == want) {      // claimed, or the key arrived there meanwhile
+                    const uint32_t prev = atomicCAS(gp + empty, LDS_EMPTY32, want);
+                    if (prev == LDS_EMPTY32 || prev == want) {  // claimed, or the key arrived there meanwhile
                         found = static_cast<int>(4 * g) + empty;
                         done = true;
                     }                                         // else: the slot went to another key; read again
