@@ -7,9 +7,12 @@
 //  3. scatter: per tile, each wave ranks its rows inside their bucket with
 //              ballots (stable: rows keep input order), the block turns ranks
 //              into tile-local positions, and every column is staged in LDS in
-//              bucket order and written out as contiguous runs.  Tiles are
-//              mapped so that each XCD works on one contiguous range of tiles,
-//              keeping the partial lines at run boundaries in one L2.
+//              bucket order and written out as contiguous runs.  Each XCD
+//              takes chunks of PT_XCD_CHUNK consecutive tiles, the chunks
+//              dealt round the XCDs in order: the partial lines at the ends of
+//              a tile's runs meet the next tile's in the same L2 (except at a
+//              chunk's end), and the eight XCDs write neighbouring stretches
+//              of each bucket.
 #include <cstdlib>
 
 #include "gq_device.h"
@@ -22,6 +25,20 @@ constexpr int PT_THREADS = 256;
 constexpr int PT_WAVES = PT_THREADS / 64;
 constexpr int PT_MAX_LOG2P = 8;
 constexpr int PT_MAX_COLS = 8;
+constexpr uint32_t PT_XCD_CHUNK = 32;
+
+// Tile of workgroup bid.  Workgroups go round the XCDs in launch order (XCD =
+// bid % GQ_NUM_XCD); the i-th workgroup of an XCD works in that XCD's
+// (i / PT_XCD_CHUNK)-th chunk.  Workgroups past the last whole round of chunks
+// keep their own index.  A bijection on [0, nblocks).
+GQ_DEV uint32_t part_tile_of(uint32_t bid, uint32_t nblocks)
+{
+    constexpr uint32_t ROUND = GQ_NUM_XCD * PT_XCD_CHUNK;
+    const uint32_t full = nblocks / ROUND * ROUND;
+    if (bid >= full) return bid;
+    const uint32_t xcd = bid % GQ_NUM_XCD, local = bid / GQ_NUM_XCD;
+    return ((local / PT_XCD_CHUNK) * GQ_NUM_XCD + xcd) * PT_XCD_CHUNK + local % PT_XCD_CHUNK;
+}
 
 struct part_cols {
     const void *in[PT_MAX_COLS];
@@ -92,7 +109,7 @@ __global__ __launch_bounds__(PT_THREADS) void part_scatter_kernel(const int64_t 
     __shared__ uint8_t lbucket[TILE];
     __shared__ uint64_t stage[TILE];
 
-    const uint32_t tile = gq_xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tile = part_tile_of(blockIdx.x, gridDim.x);
     const int64_t base = static_cast<int64_t>(tile) * TILE;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < PT_WAVES * P; i += PT_THREADS) (&wcnt[0][0])[i] = 0;
