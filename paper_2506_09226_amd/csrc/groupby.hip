@@ -188,46 +188,69 @@ GQ_DEV int lds_find(lds_table<SLOTS, K64, K32> &T, bool active, uint64_t h, int6
     int probes = 0, found = -1;
     bool done = !active;
     if constexpr (!K64) {
-        // Linear probing over groups of four slots: the four 32-bit words of
-        // a group are read together (one 16-byte load), the key is looked for
-        // in all of them, and a missing key claims the group's first empty
-        // slot with one compare-and-swap (re-reading the group if another
-        // lane took that slot first).  A key therefore sits in the first group
-        // from its home group that had room when it arrived, and slots never
-        // empty again, so a lookup may stop at the first group with an empty
-        // slot.  The wave-uniform loop runs as long as the longest chain of
-        // the wave, in groups instead of slots.
+        // Linear probing over groups of four slots.  A lookup reads its group
+        // and the next one together (two 16-byte loads), looks for the key in
+        // both, and a missing key claims the first empty slot of the first
+        // group that has one with one compare-and-swap (re-reading from that
+        // group if another lane took the slot first).  A key therefore sits
+        // in the first group from its home group that had room when it
+        // arrived, and slots never empty again, so a lookup may stop at the
+        // first group with an empty slot.  The wave-uniform loop runs as long
+        // as the longest chain of the wave; reading two groups at a time
+        // makes a second round rare (about 1% of keys overflow their home
+        // group at the tables' load, which would otherwise give most waves
+        // a lane that needs one).
         if (static_cast<uint32_t>(k32) == LDS_EMPTY32) done = true;   // the marker: the global table takes the row
         const uint32_t want = static_cast<uint32_t>(k32);
-        uint32_t g = s >> 2;
+        constexpr uint32_t NG = SLOTS / 4;
+        constexpr int LIMIT = GB_LDS_PROBES / 4;      // groups from the home group a key may sit in
+        uint32_t g = s >> 2;                          // probes = distance of g from the home group
         while (__any(!done)) {
             if (!done) {
-                uint32_t *gp = &T.word[4 * g];
-                // one 16-byte read; each word is read whole, which is all the
-                // claim protocol needs (a word only ever goes from empty to a key)
+                const uint32_t g2 = (g + 1 == NG) ? 0 : g + 1;
+                const bool two = probes + 1 < LIMIT;      // g2 is within the limit too
+                // each word is read whole, which is all the claim protocol
+                // needs (a word only ever goes from empty to a key)
                 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
                 typedef const volatile __attribute__((address_space(3))) u32x4 lds_u32x4;
-                const u32x4 wv = *(lds_u32x4 *)(gp);
-                const uint32_t w[4] = {wv.x, wv.y, wv.z, wv.w};
-                int hit = -1, empty = -1;
+                const u32x4 wa = *(lds_u32x4 *)(&T.word[4 * g]);
+                const u32x4 wb = *(lds_u32x4 *)(&T.word[4 * g2]);
+                const uint32_t w[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+                int hit1 = -1, empty1 = -1, hit2 = -1, empty2 = -1;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
-                    if (w[i] == want) hit = i;
-                    if (w[i] == LDS_EMPTY32) empty = i;
+                    if (w[i] == want) hit1 = i;
+                    if (w[i] == LDS_EMPTY32) empty1 = i;
+                    if (w[4 + i] == want) hit2 = i;
+                    if (w[4 + i] == LDS_EMPTY32) empty2 = i;
                 }
-                if (hit >= 0) {
-                    found = static_cast<int>(4 * g) + hit;
+                if (!two) hit2 = empty2 = -1;
+                if (hit1 >= 0) {
+                    found = static_cast<int>(4 * g) + hit1;
                     done = true;
-                } else if (empty >= 0) {
-                    const uint32_t prev = atomicCAS(gp + empty, LDS_EMPTY32, want);
+                } else if (empty1 >= 0) {
+                    const uint32_t prev = atomicCAS(&T.word[4 * g + empty1], LDS_EMPTY32, want);
                     if (prev == LDS_EMPTY32 || prev == want) {  // claimed, or the key arrived there meanwhile
-                        found = static_cast<int>(4 * g) + empty;
+                        found = static_cast<int>(4 * g) + empty1;
                         done = true;
                     }                                         // else: the slot went to another key; read again
-                } else if (++probes >= GB_LDS_PROBES / 4) {
+                } else if (hit2 >= 0) {                       // the first group is full
+                    found = static_cast<int>(4 * g2) + hit2;
                     done = true;
+                } else if (empty2 >= 0) {
+                    const uint32_t prev = atomicCAS(&T.word[4 * g2 + empty2], LDS_EMPTY32, want);
+                    if (prev == LDS_EMPTY32 || prev == want) {
+                        found = static_cast<int>(4 * g2) + empty2;
+                        done = true;
+                    } else {                                  // read again from the second group
+                        g = g2;
+                        probes += 1;
+                    }
+                } else if ((probes += two ? 2 : 1) >= LIMIT) {
+                    done = true;                              // every group within the limit is full
                 } else {
-                    g = (g + 1 == SLOTS / 4) ? 0 : g + 1;
+                    const uint32_t last = two ? g2 : g;
+                    g = (last + 1 == NG) ? 0 : last + 1;
                 }
             }
         }
@@ -563,7 +586,14 @@ __global__ __launch_bounds__(256) void gb_table_emit_kernel(gtable g, gq_groups 
 constexpr int GB_MAX_P = 1024;                      // buckets of the tile-staged scatter
 constexpr int GB_MAX_P_WIDE = 8192;                 // buckets of the two-level scatter
 constexpr int64_t GB_CUS = 256;                     // compute units of the MI355X
-constexpr int GB_BUCKET_ITEMS = 4;
+// Records per thread of a bucket-pass step (loaded one step ahead): four
+// 16-byte records, or two of the wider key64 records, which keeps a
+// 1024-thread workgroup's threads within their 128 registers (with four,
+// the composite-key form spilled 14 registers to scratch).
+template <bool K64>
+struct bucket_items {
+    static constexpr int value = K64 ? 2 : 4;
+};
 constexpr int GB_COMBINE_LANES = 8;                 // lanes on one slot above which a wave sums them first
 
 template <bool K64, bool K32>
@@ -1337,13 +1367,14 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
         r0 = split ? b0 + static_cast<int64_t>(ch - cstart[b]) * chunk_rows : b0;
         r1 = split ? (r0 + chunk_rows < b1 ? r0 + chunk_rows : b1) : b1;
     };
-    constexpr int STEP = GB_BUCKET_THREADS * GB_BUCKET_ITEMS;
+    constexpr int ITEMS = bucket_items<K64>::value;
+    constexpr int STEP = GB_BUCKET_THREADS * ITEMS;
     // the records of the next step are loaded while this step's are aggregated
-    int64_t nk64[GB_BUCKET_ITEMS], nq[GB_BUCKET_ITEMS], nrv[GB_BUCKET_ITEMS];
-    int32_t nk32[GB_BUCKET_ITEMS];
+    int64_t nk64[ITEMS], nq[ITEMS], nrv[ITEMS];
+    int32_t nk32[ITEMS];
     auto load_step = [&](int64_t i0, int64_t end) {
 #pragma unroll
-        for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+        for (int c = 0; c < ITEMS; ++c) {
             const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
             nk64[c] = nq[c] = nrv[c] = 0;
             nk32[c] = 0;
@@ -1374,10 +1405,10 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
         if (nitem < total) geom(nitem, nr0, nr1, nbk, nsplit);
         bool have_next = false;
         for (int64_t i0 = r0; i0 < r1; i0 += STEP) {
-            int64_t k64[GB_BUCKET_ITEMS], q[GB_BUCKET_ITEMS], rv[GB_BUCKET_ITEMS];
-            int32_t k32[GB_BUCKET_ITEMS];
+            int64_t k64[ITEMS], q[ITEMS], rv[ITEMS];
+            int32_t k32[ITEMS];
 #pragma unroll
-            for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+            for (int c = 0; c < ITEMS; ++c) {
                 k64[c] = nk64[c];
                 k32[c] = nk32[c];
                 q[c] = nq[c];
@@ -1390,7 +1421,7 @@ __global__ __launch_bounds__(GB_BUCKET_THREADS) void gb_bucket_kernel(const uint
                 have_next = true;
             }
 #pragma unroll
-            for (int c = 0; c < GB_BUCKET_ITEMS; ++c) {
+            for (int c = 0; c < ITEMS; ++c) {
                 const int64_t i = i0 + c * GB_BUCKET_THREADS + threadIdx.x;
                 const bool active = i < r1;
                 gq_i128 rev;
