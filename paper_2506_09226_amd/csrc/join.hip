@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "gq_device.h"
 #include "gq_internal.h"
@@ -695,16 +696,19 @@ GQ_DEV int64_t jx_probe_global(const jt_slot *slots, uint64_t mask, uint64_t s, 
 // place is its list's start in the tile, plus the rows of that list in
 // earlier waves, plus the rows of that list already seen by its wave, plus
 // its rank among its wave's lanes with the same list (S + 1 ballots).
-template <bool HAS_SEL>
-__global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table, const int64_t *__restrict__ fk,
+constexpr int JX_SPLIT_THREADS = 512;
+template <bool HAS_SEL, int ST>
+__global__ __launch_bounds__(ST) void jx_split_kernel(const void *table, const int64_t *__restrict__ fk,
                                                               int64_t n_bound, const int64_t *n_dev,
                                                               const int32_t *__restrict__ sel, jx_geom gm, jx_ws w,
                                                               uint32_t *status)
 {
-    constexpr int WAVES = JX_THREADS / 64;
+    constexpr int ITEMS = JX_TILE / ST;                   // rows per thread
+    constexpr int WAVES = ST / 64;
     constexpr int WROWS = JX_TILE / WAVES;
+    constexpr int LPT = (JX_LISTS + ST - 1) / ST;         // lists per thread in the list scan
     __shared__ uint32_t wcnt[WAVES][JX_LISTS];            // per wave: running counts, then prefixes
-    __shared__ uint32_t lstart[2 * JX_THREADS + 1];
+    __shared__ uint32_t lstart[LPT * ST + 1];
     __shared__ uint32_t scan_smem[WAVES];
     __shared__ int64_t stage_k[JX_TILE];
     __shared__ uint16_t stage_i[JX_TILE];
@@ -726,18 +730,18 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
     const int rbits = gm.L - JX_RBITS;
     const uint32_t stray = 1u << gm.S;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < WAVES * JX_LISTS; i += JX_THREADS) (&wcnt[0][0])[i] = 0;
-    int32_t r[JX_ITEMS];
+    for (int i = threadIdx.x; i < WAVES * JX_LISTS; i += ST) (&wcnt[0][0])[i] = 0;
+    int32_t r[ITEMS];
 #pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int q = wave * WROWS + c * 64 + lane;          // index in the tile
         r[c] = 0;
         if (q < rows) r[c] = HAS_SEL ? sel[base + q] : static_cast<int32_t>(base + q);
     }
-    int64_t k[JX_ITEMS];
-    uint32_t reg[JX_ITEMS];
+    int64_t k[ITEMS];
+    uint32_t reg[ITEMS];
 #pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int q = wave * WROWS + c * 64 + lane;
         k[c] = q < rows ? fk[r[c]] : 0;
         reg[c] = static_cast<uint32_t>(gq_fmix64(static_cast<uint64_t>(k[c])) >> (64 - rbits));
@@ -745,9 +749,9 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
     if (threadIdx.x == 0) s_hp = static_cast<int32_t>(reg[0] >> gm.S);
     __syncthreads();
     const uint32_t hp = static_cast<uint32_t>(s_hp);
-    uint32_t pos[JX_ITEMS];                               // list << 16 | rank in (wave, list)
+    uint32_t pos[ITEMS];                               // list << 16 | rank in (wave, list)
 #pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int q = wave * WROWS + c * 64 + lane;
         const bool valid = q < rows;
         const uint32_t x = (reg[c] >> gm.S) == hp ? (reg[c] & (stray - 1)) : stray;
@@ -765,11 +769,11 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
         pos[c] = (x << 16) | (old + below);
     }
     __syncthreads();
-    // per list: prefix over waves; thread i owns lists 2i and 2i + 1
-    uint32_t tot[2];
+    // per list: prefix over waves; thread i owns lists LPT i .. LPT i + LPT - 1
+    uint32_t tot[LPT];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int x = 2 * threadIdx.x + j;
+    for (int j = 0; j < LPT; ++j) {
+        const int x = LPT * threadIdx.x + j;
         uint32_t run = 0;
         if (x < JX_LISTS) {
 #pragma unroll
@@ -782,20 +786,26 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
         tot[j] = run;
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {                         // a heavy key's region: its long runs are weighed
-        const int x = 2 * threadIdx.x + j;
+    for (int j = 0; j < LPT; ++j) {                       // a heavy key's region: its long runs are weighed
+        const int x = LPT * threadIdx.x + j;
         if (x < (1 << gm.S) && tot[j] > JX_HEAVY_RUN) {
             atomicAdd(&w.rw[(hp << gm.S) + x], tot[j]);
             __hip_atomic_store(&w.ctr[16], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) mine += tot[j];
     uint32_t all;
-    const uint32_t excl = gq_block_exclusive_scan<JX_THREADS>(tot[0] + tot[1], &all, scan_smem);
-    lstart[2 * threadIdx.x] = excl;
-    lstart[2 * threadIdx.x + 1] = excl + tot[0];
-    if (threadIdx.x == 0) lstart[2 * JX_THREADS] = all;
+    uint32_t excl = gq_block_exclusive_scan<ST>(mine, &all, scan_smem);
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+        lstart[LPT * threadIdx.x + j] = excl;
+        excl += tot[j];
+    }
+    if (threadIdx.x == 0) lstart[LPT * ST] = all;
     __syncthreads();
-    for (uint32_t x = threadIdx.x; x <= stray + 1; x += JX_THREADS)
+    for (uint32_t x = threadIdx.x; x <= stray + 1; x += ST)
         w.starts[tile * JX_STARTS + x] = static_cast<uint16_t>(lstart[x]);
     if (threadIdx.x == 0) {
         w.tile_hp[tile] = static_cast<int32_t>(hp);
@@ -803,7 +813,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
         atomicMax(&w.hp_end[hp], static_cast<uint32_t>(tile + 1));
     }
 #pragma unroll
-    for (int c = 0; c < JX_ITEMS; ++c) {
+    for (int c = 0; c < ITEMS; ++c) {
         const int q = wave * WROWS + c * 64 + lane;
         if (q < rows) {
             const uint32_t x = pos[c] >> 16;
@@ -817,7 +827,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_split_kernel(const void *table,
         }
     }
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < static_cast<uint32_t>(rows); q += JX_THREADS) {
+    for (uint32_t q = threadIdx.x; q < static_cast<uint32_t>(rows); q += ST) {
         w.skey[base + q] = stage_k[q];
         w.sidx[base + q] = stage_i[q];
     }
@@ -851,15 +861,19 @@ __global__ __launch_bounds__(JX_PLAN_THREADS) void jx_plan_kernel(const uint32_t
 }
 
 // Region probes from LDS (see above).  Persistent: work items (a region, or
-// one tile range of a heavy region) come from w.ctr[0].
-__global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table, jx_geom gm, jx_ws w)
+// one tile range of a heavy region) come from w.ctr[0].  RT threads: a batch
+// is RT tiles, a window gives each thread JX_WIN / RT entries.
+constexpr int JR_THREADS_PROBE = 512;
+template <int RT>
+__global__ __launch_bounds__(RT) void jx_region_kernel(const void *table, jx_geom gm, jx_ws w)
 {
+    using map_t = std::conditional_t<(RT <= 256), uint8_t, uint16_t>;
     __shared__ __align__(16) int64_t lkey[JX_REGION];
     __shared__ int32_t lpay[JX_REGION];
-    __shared__ uint8_t map[JX_WIN];                       // window entry -> batch tile (thread)
-    __shared__ int32_t b_at[JX_THREADS];                  // pool position of each batch tile's run
-    __shared__ uint32_t b_pos[JX_THREADS];                // exclusive prefix of the runs' lengths
-    __shared__ uint32_t scan_smem[JX_THREADS / 64];
+    __shared__ map_t map[JX_WIN];                         // window entry -> batch tile (thread)
+    __shared__ int32_t b_at[RT];                          // pool position of each batch tile's run
+    __shared__ uint32_t b_pos[RT];                        // exclusive prefix of the runs' lengths
+    __shared__ uint32_t scan_smem[RT / 64];
     __shared__ int64_t s_item;
     if (static_cast<const jt_header *>(table)->log2_slots != static_cast<uint32_t>(gm.L)) return;   // uniform
     const jt_slot *slots = reinterpret_cast<const jt_slot *>(static_cast<const char *>(table) + JT_HEADER);
@@ -888,7 +902,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
         const uint32_t hp = static_cast<uint32_t>(item) >> gm.S;
         const uint32_t sub = static_cast<uint32_t>(item) & ((1u << gm.S) - 1);
         const jt_slot *rs = slots + (static_cast<uint64_t>(item) << JX_RBITS);
-        for (int j = threadIdx.x; j < JX_REGION; j += JX_THREADS) {
+        for (int j = threadIdx.x; j < JX_REGION; j += RT) {
             const int4 v = *reinterpret_cast<const int4 *>(&rs[j]);
             lkey[j] = (static_cast<int64_t>(static_cast<uint32_t>(v.y)) << 32) | static_cast<uint32_t>(v.x);
             lpay[j] = v.z;
@@ -919,12 +933,12 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
         // order LDS alone: the region's loads, the next batch's run lookups
         // and the result stores stay in flight across them.
         gq_lds_barrier();                                  // the region is in LDS
-        for (int64_t t0 = t_lo; t0 < t_hi; t0 += JX_THREADS) {
+        for (int64_t t0 = t_lo; t0 < t_hi; t0 += RT) {
             uint32_t nlen;
             int32_t nat;
-            run_of(t0 + JX_THREADS + threadIdx.x, nlen, nat);      // next batch, in flight meanwhile
+            run_of(t0 + RT + threadIdx.x, nlen, nat);      // next batch, in flight meanwhile
             uint32_t total;
-            const uint32_t pos = gq_block_exclusive_scan_lds<JX_THREADS>(len, &total, scan_smem);
+            const uint32_t pos = gq_block_exclusive_scan_lds<RT>(len, &total, scan_smem);
             b_at[threadIdx.x] = at;
             b_pos[threadIdx.x] = pos;
             const uint32_t ntot = static_cast<uint32_t>(gq_uniform(total));
@@ -932,15 +946,15 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
                 gq_lds_barrier();                          // previous window done with map; b_* written
                 const uint32_t a = pos > w0 ? pos : w0;
                 const uint32_t e = (pos + len < w0 + JX_WIN) ? pos + len : w0 + JX_WIN;
-                for (uint32_t j = a; j < e; ++j) map[j - w0] = static_cast<uint8_t>(threadIdx.x);
+                for (uint32_t j = a; j < e; ++j) map[j - w0] = static_cast<map_t>(threadIdx.x);
                 gq_lds_barrier();
                 const uint32_t cnt = ntot - w0 < JX_WIN ? ntot - w0 : JX_WIN;
-                constexpr int PER = JX_WIN / JX_THREADS;
+                constexpr int PER = JX_WIN / RT;
                 int64_t k[PER];
                 int32_t pa[PER];
 #pragma unroll
                 for (int c = 0; c < PER; ++c) {
-                    const uint32_t q = c * JX_THREADS + threadIdx.x;
+                    const uint32_t q = c * RT + threadIdx.x;
                     pa[c] = -1;
                     k[c] = JT_EMPTY;
                     if (q < cnt) {
@@ -1020,19 +1034,20 @@ __global__ __launch_bounds__(JX_THREADS) void jx_region_kernel(const void *table
 // current one; its barriers order LDS only, so those loads stay in flight.
 // Look-back cannot deadlock: the smallest unfinished tile is always some
 // workgroup's current tile, and it waits only on smaller tiles.
-template <bool HAS_SEL>
-__global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t n_bound, const int64_t *n_dev,
+template <bool HAS_SEL, int CT>
+__global__ __launch_bounds__(CT) void jx_compact_kernel(jx_ws w, int64_t n_bound, const int64_t *n_dev,
                                                                 const int32_t *__restrict__ sel,
                                                                 int32_t *__restrict__ prow_out,
                                                                 int32_t *__restrict__ pay_out, int64_t *n_out)
 {
-    // LDS index x is stored at x + x / 16: a thread's 16 consecutive elements
-    // then start 17 words after its neighbour's, on another bank
-    __shared__ int32_t pay[JX_TILE + JX_TILE / 16];       // payloads in probe order; then the staged payloads
-    __shared__ uint16_t stage_i[JX_TILE + JX_TILE / 16];  // in-tile index of each staged match
-    auto pad = [](uint32_t x) { return x + (x >> 4); };
+    constexpr int CI = JX_TILE / CT;                      // tile elements per thread (16 or 8)
+    // LDS index x is stored at x + x / CI: a thread's CI consecutive elements
+    // then start CI + 1 words after its neighbour's, on another bank
+    __shared__ int32_t pay[JX_TILE + JX_TILE / CI];       // payloads in probe order; then the staged payloads
+    __shared__ uint16_t stage_i[JX_TILE + JX_TILE / CI];  // in-tile index of each staged match
+    auto pad = [](uint32_t x) { return x + x / CI; };
     __shared__ uint32_t hitw[JX_TILE / 32];               // hit bitmap in probe order
-    __shared__ uint32_t scan_smem[JX_THREADS / 64];
+    __shared__ uint32_t scan_smem[CT / 64];
     __shared__ uint32_t s_next;
     __shared__ uint64_t s_goff;
     const int64_t n = jx_eff_n(n_bound, n_dev);
@@ -1044,8 +1059,8 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
     }
     auto load_tile = [&](int64_t t, uint16_t *ix, int64_t *rv) {
 #pragma unroll
-        for (int c = 0; c < JX_ITEMS; ++c) {
-            const int64_t p = t * JX_TILE + c * JX_THREADS + threadIdx.x;     // pool position
+        for (int c = 0; c < CI; ++c) {
+            const int64_t p = t * JX_TILE + c * CT + threadIdx.x;             // pool position
             ix[c] = 0;
             rv[c] = -1;
             if (t < ntiles && p < n) {
@@ -1057,8 +1072,8 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
     if (threadIdx.x == 0) s_next = atomicAdd(&w.ctr[32], 1u);
     __syncthreads();
     int64_t t = static_cast<int64_t>(gq_uniform(s_next));
-    uint16_t ix[JX_ITEMS];
-    int64_t rv[JX_ITEMS];
+    uint16_t ix[CI];
+    int64_t rv[CI];
     load_tile(t, ix, rv);
     while (t < ntiles) {
         // a barrier opens each pass, so thread-0 work of consecutive passes
@@ -1073,8 +1088,8 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
         gq_lds_barrier();
         if (threadIdx.x == 0) s_next = nxt;
 #pragma unroll
-        for (int c = 0; c < JX_ITEMS; ++c) {
-            const int64_t p = base + c * JX_THREADS + threadIdx.x;
+        for (int c = 0; c < CI; ++c) {
+            const int64_t p = base + c * CT + threadIdx.x;
             if (p < n) {
                 pay[pad(ix[c])] = static_cast<int32_t>(rv[c]);
                 if (rv[c] >= 0) atomicOr(&hitw[ix[c] >> 5], 1u << (ix[c] & 31));
@@ -1087,21 +1102,21 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
             const uint32_t c = __popc(hitw[lane]) + __popc(hitw[lane + 64]);
             gq_lookback_publish(w.status, static_cast<uint32_t>(t), gq_wave_sum(c));
         }
-        // thread i owns probe-order elements [16 i, 16 i + 16)
-        const int elem0 = threadIdx.x * JX_ITEMS;
-        const uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & 0xffffu;
-        int32_t my_pay[JX_ITEMS];
+        // thread i owns probe-order elements [CI i, CI i + CI)
+        const int elem0 = threadIdx.x * CI;
+        const uint32_t mine = (hitw[elem0 >> 5] >> (elem0 & 31)) & ((1u << CI) - 1u);
+        int32_t my_pay[CI];
 #pragma unroll
-        for (int i = 0; i < JX_ITEMS; ++i) my_pay[i] = pay[pad(elem0 + i)];
+        for (int i = 0; i < CI; ++i) my_pay[i] = pay[pad(elem0 + i)];
         uint32_t total;
-        uint32_t pos = gq_block_exclusive_scan_lds<JX_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
+        uint32_t pos = gq_block_exclusive_scan_lds<CT>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
         if (wave == 0) {
             const uint64_t g = gq_lookback_wait(w.status, static_cast<uint32_t>(t), total);
             if (lane == 0) s_goff = g;
         }
         // the scan's barriers ordered every read of pay[] before these writes
 #pragma unroll
-        for (int i = 0; i < JX_ITEMS; ++i) {
+        for (int i = 0; i < CI; ++i) {
             if (mine & (1u << i)) {
                 stage_i[pad(pos)] = static_cast<uint16_t>(elem0 + i);
                 pay[pad(pos)] = my_pay[i];
@@ -1111,11 +1126,11 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
         gq_lds_barrier();
         const int64_t goff = static_cast<int64_t>(s_goff);
         const uint32_t tot = static_cast<uint32_t>(gq_uniform(total));
-        for (uint32_t i0 = 0; i0 < tot; i0 += JX_THREADS * 4) {
+        for (uint32_t i0 = 0; i0 < tot; i0 += CT * 4) {
             int32_t rw[4], py[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const uint32_t i = i0 + c * JX_THREADS + threadIdx.x;
+                const uint32_t i = i0 + c * CT + threadIdx.x;
                 rw[c] = 0;
                 py[c] = 0;
                 if (i < tot) {
@@ -1126,7 +1141,7 @@ __global__ __launch_bounds__(JX_THREADS) void jx_compact_kernel(jx_ws w, int64_t
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const uint32_t i = i0 + c * JX_THREADS + threadIdx.x;
+                const uint32_t i = i0 + c * CT + threadIdx.x;
                 if (i < tot) {
                     prow_out[goff + i] = rw[c];
                     pay_out[goff + i] = py[c];
@@ -1267,12 +1282,14 @@ gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table
     // counters, tile bounds and look-back words (the prefix up to the tile table)
     GQ_TRY(gq_zero(ctx, ws, static_cast<size_t>(reinterpret_cast<char *>(w.tile_hp) - static_cast<char *>(ws)) / 4, s));
     const uint32_t tiles = static_cast<uint32_t>(w.ntiles);
+    // 512-thread split workgroups: 86 VGPRs and 51 KB of LDS, 16 waves per CU
+    // (256-thread ones at 144 VGPRs fit 12)
     if (sel)
-        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true>, dim3(tiles), dim3(JX_THREADS), 0, s, table,
-                         fk, n, n_dev, sel, gm, w, ctx->status_dev));
+        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<true, JX_SPLIT_THREADS>, dim3(tiles),
+                         dim3(JX_SPLIT_THREADS), 0, s, table, fk, n, n_dev, sel, gm, w, ctx->status_dev));
     else
-        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false>, dim3(tiles), dim3(JX_THREADS), 0, s,
-                         table, fk, n, n_dev, sel, gm, w, ctx->status_dev));
+        GQ_TRY(gq_launch(ctx, "gq_join_probe_split", jx_split_kernel<false, JX_SPLIT_THREADS>, dim3(tiles),
+                         dim3(JX_SPLIT_THREADS), 0, s, table, fk, n, n_dev, sel, gm, w, ctx->status_dev));
     // a region with more rows in heavy runs than 4x the mean region (and at
     // least 65,536) is split into items of that many rows
     const int64_t item_rows = std::max<int64_t>(65536, 4 * (n / gm.nregions));
@@ -1280,16 +1297,17 @@ gq_status gq_join_probe_partitioned(gq_ctx *ctx, const void *table, size_t table
                      static_cast<const uint32_t *>(w.rw), gm.nregions,
                      static_cast<uint32_t>(std::min<int64_t>(item_rows, 1ll << 31)),
                      static_cast<const uint32_t *>(w.ctr + 16), w.iprefix));
-    const int64_t want = static_cast<int64_t>(ctx->num_cus) * 3;      // three 52-KB-LDS workgroups per CU
-    const uint32_t grid = static_cast<uint32_t>(want);
-    GQ_TRY(gq_launch(ctx, "gq_join_probe_regions", jx_region_kernel, dim3(grid), dim3(JX_THREADS), 0, s, table, gm,
-                     w));
+    // two 512-thread, 57-KB-LDS workgroups per CU (16 waves; with 256-thread
+    // workgroups at 163 VGPRs only 12 waves fit)
+    const uint32_t grid = static_cast<uint32_t>(ctx->num_cus) * 2;
+    GQ_TRY(gq_launch(ctx, "gq_join_probe_regions", jx_region_kernel<JR_THREADS_PROBE>, dim3(grid),
+                     dim3(JR_THREADS_PROBE), 0, s, table, gm, w));
     // persistent compaction: four workgroups per CU (122 VGPRs)
     const uint32_t cgrid = static_cast<uint32_t>(std::min<int64_t>(w.ntiles, static_cast<int64_t>(ctx->num_cus) * 4));
     if (sel)
-        return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true>, dim3(cgrid), dim3(JX_THREADS), 0, s,
-                         w, n, n_dev, sel, prow_out, payload_out, n_out_dev);
-    return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<false>, dim3(cgrid), dim3(JX_THREADS), 0, s, w,
-                     n, n_dev, sel, prow_out, payload_out, n_out_dev);
+        return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<true, JX_THREADS>, dim3(cgrid),
+                         dim3(JX_THREADS), 0, s, w, n, n_dev, sel, prow_out, payload_out, n_out_dev);
+    return gq_launch(ctx, "gq_join_probe_compact", jx_compact_kernel<false, JX_THREADS>, dim3(cgrid),
+                     dim3(JX_THREADS), 0, s, w, n, n_dev, sel, prow_out, payload_out, n_out_dev);
 }
 }  // extern "C"
