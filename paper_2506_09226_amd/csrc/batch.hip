@@ -31,7 +31,8 @@
 
 namespace {
 
-constexpr int BT_THREADS = 256;
+constexpr int BT_THREADS = 512;               // 84 VGPRs: three workgroups (24 waves) per CU
+constexpr int BT_TILE_GRAIN = 256;            // build and fill tiles are multiples of this
 constexpr int BT_LDS_GROUP_SLOTS = 1024;
 constexpr int BT_REGION_SLOTS = 4096;              // tables up to this size are built in LDS
 constexpr int64_t BT_EMPTY = INT64_MIN;
@@ -294,10 +295,10 @@ __device__ void item_init(const bt_inst &I, int64_t tile, int init_tile)
     }
 }
 
-// Build tile: keys in groups of 8 per thread, so their first
+// Build tile: keys in groups of BT_BUILD_ITEMS per thread, so their first
 // compare-and-swap attempts (one slot each, usually a free one at load
 // factor <= 0.9) are in flight together; collisions then walk on one by one.
-constexpr int BT_BUILD_ITEMS = 8;
+constexpr int BT_BUILD_ITEMS = 4;
 
 __device__ void item_build(const bt_inst &I, int64_t tile, int build_tile, uint32_t *status)
 {
@@ -360,7 +361,7 @@ __device__ void item_build(const bt_inst &I, int64_t tile, int build_tile, uint3
 // chunk runs in phases over its 8 rows (dates; foreign keys of the kept
 // rows; table slots; value columns of the matches; LDS aggregation), so a
 // phase's loads are all in flight together.
-constexpr int BT_CHUNK_ITEMS = 8;
+constexpr int BT_CHUNK_ITEMS = 4;
 constexpr int BT_CHUNK = BT_THREADS * BT_CHUNK_ITEMS;
 
 __device__ void item_probe(const bt_inst &I, int64_t tile, int tile_rows, bt_lds &T, uint32_t *status)
@@ -590,8 +591,8 @@ struct bt_plan {
 bool valid_tuning(const gq_tuning &t)
 {
     return t.load_factor > 0.0 && t.load_factor <= 0.9 && t.probe_tile >= 4096 && t.probe_tile % 4096 == 0 &&
-           t.probe_tile <= (1 << 22) && t.build_tile >= BT_THREADS && t.build_tile % BT_THREADS == 0 &&
-           t.init_tile >= BT_THREADS && t.init_tile % BT_THREADS == 0 && t.lag >= 0 && t.lag <= 1024 &&
+           t.probe_tile <= (1 << 22) && t.build_tile >= BT_TILE_GRAIN && t.build_tile % BT_TILE_GRAIN == 0 &&
+           t.init_tile >= BT_TILE_GRAIN && t.init_tile % BT_TILE_GRAIN == 0 && t.lag >= 0 && t.lag <= 1024 &&
            t.fanout >= 1 && t.fanout <= 64;
 }
 
