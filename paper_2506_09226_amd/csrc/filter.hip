@@ -13,9 +13,11 @@
 
 namespace {
 
-constexpr int FT_THREADS = 256;
-constexpr int FT_ITEMS = 32;
+constexpr int FT_THREADS = 512;
+constexpr int FT_ITEMS = 16;
 constexpr int FT_TILE = FT_THREADS * FT_ITEMS;     // 8192 rows
+constexpr int FT_RPT = FT_TILE / FT_THREADS;       // rows of a tile each thread owns in the write-out (16)
+constexpr int FT_TPW = 64 / FT_RPT;                // threads per bitmap word
 constexpr int FT_WORDS = FT_TILE / 64;              // 128 bitmap words
 constexpr int FT_GROUP = 4;                         // tiles per dequeue
 
@@ -99,9 +101,12 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
         }
     }
     __syncthreads();
-    // thread i owns rows [32 i, 32 i + 32) of every tile
-    for (int i = 0; i < nt; ++i)
-        cnt += __popc(static_cast<uint32_t>(bits[i][threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32)));
+    // thread i owns rows [FT_RPT i, FT_RPT i + FT_RPT) of every tile
+    auto owned = [&](int i) {
+        const uint64_t word = bits[i][threadIdx.x / FT_TPW] >> ((threadIdx.x % FT_TPW) * FT_RPT);
+        return static_cast<uint32_t>(word) & static_cast<uint32_t>((1ull << FT_RPT) - 1);
+    };
+    for (int i = 0; i < nt; ++i) cnt += __popc(owned(i));
     uint32_t gtotal;
     (void)gq_block_exclusive_scan<FT_THREADS>(cnt, &gtotal, scan_smem);
     if (wave == 0) {
@@ -112,11 +117,11 @@ __global__ __launch_bounds__(FT_THREADS) void filter_kernel(const T *__restrict_
     int64_t goff = static_cast<int64_t>(s_goff);
     for (int i = 0; i < nt; ++i) {
         const int64_t base = (t0 + i) * FT_TILE;
-        uint32_t mine = static_cast<uint32_t>(bits[i][threadIdx.x >> 1] >> ((threadIdx.x & 1) * 32));
+        uint32_t mine = owned(i);
         uint32_t total;
         uint32_t pos =
             gq_block_exclusive_scan_lds<FT_THREADS>(static_cast<uint32_t>(__popc(mine)), &total, scan_smem);
-        const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * 32;
+        const int64_t row0 = base + static_cast<int64_t>(threadIdx.x) * FT_RPT;
         while (mine) {
             const int k = __builtin_ctz(mine);
             mine &= mine - 1;
