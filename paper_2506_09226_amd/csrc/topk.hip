@@ -21,8 +21,8 @@
 
 namespace {
 
-constexpr int TK_THREADS = 256;
-constexpr int TK_STEP_ITEMS = 8;
+constexpr int TK_THREADS = 512;
+constexpr int TK_STEP_ITEMS = 4;
 constexpr int TK_STEP = TK_THREADS * TK_STEP_ITEMS;  // rows per step
 constexpr int TK_CAP = 4096;                          // LDS candidates
 constexpr int TK_MAX_K = TK_CAP - TK_STEP;            // 2048
@@ -382,7 +382,7 @@ tk_ws tk_layout(gq_carver &c, int64_t n, int k, int num_cus)
 {
     tk_ws w;
     int64_t blocks = (n + 4 * TK_STEP - 1) / (4 * TK_STEP);     // at least 4 steps per block
-    const int64_t maxb = static_cast<int64_t>(num_cus) * 3;
+    const int64_t maxb = static_cast<int64_t>(num_cus) * 2;    // two 512-thread workgroups fit a CU (95 VGPRs)
     if (blocks > maxb) blocks = maxb;
     if (blocks < 1) blocks = 1;
     int64_t chunk = (n + blocks - 1) / blocks;
