@@ -94,8 +94,11 @@ def test_filter_extremes(ctx):
 # --------------------------------------------------------------- partition ---
 
 @pytest.mark.parametrize("log2p", [0, 1, 3, 6, 8])
-@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 70_001])
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097, 70_001, 771 * 4096 + 1])
 def test_partition(ctx, log2p, n):
+    """Stable partition against the oracle; the largest size spans three
+    whole rounds of 32-tile chunks dealt over the eight XCDs (768 tiles)
+    plus a tail of tiles that keep their own index."""
     r = rng(n * 10 + log2p)
     key = r.integers(-(1 << 63), (1 << 63) - 1, size=n, dtype=np.int64)
     c32 = r.integers(0, 2557, size=n).astype(np.int32)
@@ -195,6 +198,47 @@ def test_join_build_paths(ctx, build_path, m, lf):
     fk = fk.astype(np.int64)
     table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), load_factor=lf)
     assert ctx.status() == gq.GQ_OK
+    ep, ey = oracle.join(bkey, bpay, fk)
+    prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(fk))
+    k = int(cnt.item())
+    assert k == len(ep) and np.array_equal(host(prow, k), ep) and np.array_equal(host(pay, k), ey)
+
+
+def _fmix64_inv_np(h):
+    """Inverse of the MurmurHash3 64-bit finalizer: xor-shifts by 33 undo
+    themselves, and each multiplier is undone by its inverse modulo 2^64."""
+    h = h.astype(np.uint64)
+    inv2 = np.uint64(pow(0xC4CEB9FE1A85EC53, -1, 1 << 64))
+    inv1 = np.uint64(pow(0xFF51AFD7ED558CCD, -1, 1 << 64))
+    h ^= h >> np.uint64(33)
+    h *= inv2
+    h ^= h >> np.uint64(33)
+    h *= inv1
+    h ^= h >> np.uint64(33)
+    return h
+
+
+@pytest.mark.parametrize("build_path", ["region"], indirect=True)
+def test_join_region_build_uneven_buckets(ctx, build_path):
+    """Keys whose hashes all have their top 4 bits clear fill 16 of the 256
+    first-level buckets of the region sort and leave 240 empty; 2^22 slots
+    give 2^10 regions, so each bucket is split 4 ways by the second level.
+    The table still answers every probe as the oracle does."""
+    r = rng(4242)
+    m = 200_000
+    h = np.unique(r.integers(0, 1 << 60, size=m + 1000, dtype=np.uint64))[:m]
+    r.shuffle(h)
+    bkey = _fmix64_inv_np(h).view(np.int64)
+    assert np.array_equal(_fmix64_np(bkey.view(np.uint64)), h)            # the keys hash back
+    assert not np.any(bkey == np.iinfo(np.int64).min)
+    bpay = r.integers(-(1 << 31), (1 << 31) - 1, size=m).astype(np.int32)
+    lf = 0.05
+    assert gq.gq_join_table_bytes(m, lf) == 256 + (1 << 22) * 16       # 2^10 regions of 4096 slots
+    table = gq.gq_join_build(ctx, dev(bkey), dev(bpay), load_factor=lf)
+    assert ctx.status() == gq.GQ_OK
+    n = 300_000
+    fk = np.where(r.random(n) < 0.9, bkey[r.integers(0, m, size=n)], r.integers(-(1 << 62), 1 << 62, size=n))
+    fk = fk.astype(np.int64)
     ep, ey = oracle.join(bkey, bpay, fk)
     prow, pay, cnt = gq.gq_join_probe(ctx, table, dev(fk))
     k = int(cnt.item())
